@@ -1,0 +1,157 @@
+"""ctypes wrapper over ``libace_oracle.so`` -- TEST INFRASTRUCTURE ONLY.
+
+The C library is the plain definition of the attestation check (FIPS 180-4
+SHA-256, RFC 2104 HMAC, RFC 5869 HKDF; the paper's Def. 2.1, Def. 3.1 and
+Alg. 1 Phase 1a).  This module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ace_oracle.c")
+_LIB = os.path.join(_HERE, "libace_oracle.so")
+_lib = None
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, pthreads)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-o", tmp, _SRC, "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    sz = ctypes.c_size_t
+    lib.oracle_constants.argtypes = [_u32p, _u32p]
+    lib.oracle_sha256.argtypes = [_u8p, sz, _u8p]
+    lib.oracle_sha256_compress.argtypes = [_u32p, _u8p]
+    lib.oracle_sha256_iv.argtypes = [_u32p]
+    lib.oracle_hmac_sha256.argtypes = [_u8p, sz, _u8p, sz, _u8p]
+    lib.oracle_hmac_midstates.argtypes = [_u8p, sz, _u32p]
+    lib.oracle_hkdf_sha256.argtypes = [_u8p, sz, _u8p, sz, _u8p, sz, _u8p, sz]
+    lib.oracle_hkdf_sha256.restype = ctypes.c_int
+    lib.oracle_derive_keys.argtypes = [_u8p, ctypes.c_uint32, _u8p, sz, _u8p, sz, _u8p,
+                                       ctypes.c_int]
+    lib.oracle_verify_batch.argtypes = [_u8p, ctypes.c_uint32, _u8p, _u64p, _u32p, _u8p,
+                                        ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _buf(b) -> ctypes.Array:
+    b = bytes(b)
+    return (ctypes.c_uint8 * max(1, len(b))).from_buffer_copy(b if b else b"\0")
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def constants() -> tuple[np.ndarray, np.ndarray]:
+    """(K[64], H0[8]) as the oracle computes them from the primes."""
+    k = np.zeros(64, np.uint32)
+    iv = np.zeros(8, np.uint32)
+    _load().oracle_constants(_ptr(k, _u32p), _ptr(iv, _u32p))
+    return k, iv
+
+
+def sha256(msg: bytes) -> bytes:
+    out = (ctypes.c_uint8 * 32)()
+    _load().oracle_sha256(_buf(msg), len(msg), out)
+    return bytes(out)
+
+
+def sha256_iv() -> np.ndarray:
+    h = np.zeros(8, np.uint32)
+    _load().oracle_sha256_iv(_ptr(h, _u32p))
+    return h
+
+
+def sha256_compress(state, block: bytes) -> np.ndarray:
+    """One FIPS 180-4 block computation F(state, block); returns the new state."""
+    assert len(block) == 64
+    h = np.array(state, dtype=np.uint32).copy()
+    _load().oracle_sha256_compress(_ptr(h, _u32p), _buf(block))
+    return h
+
+
+def hmac_sha256(key: bytes, msg: bytes) -> bytes:
+    out = (ctypes.c_uint8 * 32)()
+    _load().oracle_hmac_sha256(_buf(key), len(key), _buf(msg), len(msg), out)
+    return bytes(out)
+
+
+def hmac_midstates(keys: np.ndarray) -> np.ndarray:
+    """[n][32] keys -> [n][16] u32: ipad state words 0-7, opad state 8-15."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+    out = np.zeros((keys.shape[0], 16), np.uint32)
+    lib = _load()
+    for j in range(keys.shape[0]):
+        lib.oracle_hmac_midstates(_buf(keys[j].tobytes()), 32,
+                                  out[j].ctypes.data_as(_u32p))
+    return out
+
+
+def hkdf_sha256(salt: bytes | None, ikm: bytes, info: bytes, length: int) -> bytes:
+    out = (ctypes.c_uint8 * max(1, length))()
+    s = b"" if salt is None else salt
+    rc = _load().oracle_hkdf_sha256(_buf(s), len(s), _buf(ikm), len(ikm), _buf(info),
+                                    len(info), out, length)
+    if rc != 0:
+        raise ValueError("HKDF output length exceeds 255 * 32")
+    return bytes(out)[:length]
+
+
+def derive_keys(rev: np.ndarray, salt: bytes, info: bytes, nthreads: int = 1) -> np.ndarray:
+    """k_j = HKDF(salt, IKM = rev[j], info, 32) for every identity j."""
+    rev = np.ascontiguousarray(rev, dtype=np.uint8).reshape(-1, 32)
+    keys = np.zeros_like(rev)
+    _load().oracle_derive_keys(_ptr(rev, _u8p), rev.shape[0], _buf(salt), len(salt),
+                               _buf(info), len(info), _ptr(keys, _u8p), nthreads)
+    return keys
+
+
+def verify_batch(keys: np.ndarray, msg: np.ndarray, off: np.ndarray, ids: np.ndarray,
+                 tags: np.ndarray, nthreads: int = 1) -> tuple[np.ndarray, int]:
+    """Bitmask (u32 words, LSB-first) and valid count for one block of txs."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+    msg = np.ascontiguousarray(msg, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    tags = np.ascontiguousarray(tags, dtype=np.uint8).reshape(-1, 32)
+    n = ids.shape[0]
+    assert off.shape[0] == n + 1 and tags.shape[0] == n
+    mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
+    cnt = ctypes.c_uint64(0)
+    msg_arg = msg if msg.size else np.zeros(1, np.uint8)
+    _load().oracle_verify_batch(_ptr(keys, _u8p) if keys.size else None, keys.shape[0],
+                                _ptr(msg_arg, _u8p), _ptr(off, _u64p), _ptr(ids, _u32p),
+                                _ptr(tags, _u8p) if tags.size else None, n,
+                                _ptr(mask, _u32p), ctypes.byref(cnt), nthreads)
+    return mask[: (n + 31) // 32], int(cnt.value)
+
+
+def verify_batch_rev(rev: np.ndarray, salt: bytes, info: bytes, msg, off, ids, tags,
+                     nthreads: int = 1) -> tuple[np.ndarray, int]:
+    """Keys derived from REV by HKDF first (Alg. 1 Phase 1a), then verified."""
+    keys = derive_keys(rev, salt, info, nthreads)
+    return verify_batch(keys, msg, off, ids, tags, nthreads)

@@ -1,0 +1,295 @@
+"""Seeded synthetic workloads for the attestation check.
+
+This module only draws random numbers (numpy PCG64) and lays them out the way
+the verifier consumes them.  The credentials a client would attach (the
+paper's Alg. 2, GenerateAttestation) are produced by the host's OpenSSL
+through ``attest_client.c``; no hash arithmetic lives here.  The truth mask is
+the corruption plan itself, so it is a witness independent of both the CPU
+oracle and the GPU library.
+
+Shapes follow the paper's workloads: 32-byte root entropy per identity
+(Def. 2.1), a 32-byte credential per transaction (Def. 3.1), identities
+chosen uniformly or Zipf-skewed, and message lengths fixed, uniform or
+lognormal.  Every draw comes from ``SeedSequence(0xACE0 + config_no)``
+spawned into independent child streams, one per quantity.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+INFO_16 = b"ACEGF-V1-MEMPOOL"            # 16-byte purpose string (first 16 bytes of the next)
+INFO_ATTEST = b"ACEGF-V1-MEMPOOL-ATTEST"  # purpose string of equation attestkey
+
+KIND_TAG, KIND_MSG, KIND_KEY = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_CLIENT_SRC = os.path.join(_HERE, "attest_client.c")
+_CLIENT_LIB = os.path.join(_HERE, "libace_client.so")
+_client = None
+
+
+def build_client(force: bool = True) -> str:
+    if force or not os.path.exists(_CLIENT_LIB):
+        tmp = _CLIENT_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp,
+                               _CLIENT_SRC, "-lcrypto", "-lpthread"])
+        os.replace(tmp, _CLIENT_LIB)
+    return _CLIENT_LIB
+
+
+def _lib():
+    global _client
+    if _client is None:
+        if not os.path.exists(_CLIENT_LIB):
+            build_client(force=False)
+        lib = ctypes.CDLL(_CLIENT_LIB)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        lib.client_derive_keys.argtypes = [vp, ctypes.c_uint64, vp, sz, vp, sz, vp, ctypes.c_int]
+        lib.client_sign.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
+        _client = lib
+    return _client
+
+
+def host_threads() -> int:
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(16, n or 1))
+
+
+def client_keys(rev: np.ndarray, salt: bytes, info: bytes, nthreads: int | None = None) -> np.ndarray:
+    """Client-side keys (OpenSSL HKDF-SHA256, 32 bytes) for every identity."""
+    rev = np.ascontiguousarray(rev, dtype=np.uint8).reshape(-1, 32)
+    keys = np.zeros_like(rev)
+    sb, ib = (ctypes.c_char * max(1, len(salt))).from_buffer_copy(salt or b"\0"), \
+        (ctypes.c_char * max(1, len(info))).from_buffer_copy(info or b"\0")
+    rc = _lib().client_derive_keys(rev.ctypes.data, rev.shape[0], sb, len(salt), ib, len(info),
+                                   keys.ctypes.data, nthreads or host_threads())
+    if rc != 0:
+        raise RuntimeError("OpenSSL HKDF failed (%d)" % rc)
+    return keys
+
+
+def client_sign(keys: np.ndarray, msg: np.ndarray, off: np.ndarray, key_index: np.ndarray,
+                nthreads: int | None = None) -> np.ndarray:
+    """Client-side credentials (OpenSSL HMAC-SHA256) for every transaction."""
+    n = key_index.shape[0]
+    tags = np.zeros((n, 32), np.uint8)
+    if n == 0:
+        return tags
+    keys = np.ascontiguousarray(keys, dtype=np.uint8)
+    msg_arg = msg if msg.size else np.zeros(1, np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    key_index = np.ascontiguousarray(key_index, dtype=np.uint32)
+    rc = _lib().client_sign(keys.ctypes.data, msg_arg.ctypes.data, off.ctypes.data,
+                            key_index.ctypes.data, n, tags.ctypes.data,
+                            nthreads or host_threads())
+    if rc != 0:
+        raise RuntimeError("OpenSSL HMAC failed (%d)" % rc)
+    return tags
+
+
+@dataclasses.dataclass
+class Workload:
+    """One batch of transactions plus the identity registry it refers to."""
+    name: str
+    rev: np.ndarray          # [n_id][32] u8 root entropy
+    salt: bytes              # shared HKDF salt (the context)
+    info: bytes              # HKDF purpose string
+    msg: np.ndarray          # u8, all messages back to back
+    off: np.ndarray          # u64 [n+1] byte offsets into msg
+    ids: np.ndarray          # u32 [n] identity index of each tx
+    tags: np.ndarray         # u8 [n][32] credential of each tx
+    truth: np.ndarray        # bool [n] the generator's verdict (corruption plan)
+    keys: np.ndarray         # u8 [n_id][32] client-side keys (OpenSSL)
+    block_sizes: Optional[np.ndarray] = None   # for multi-block batches
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.ids.shape[0])
+
+    @property
+    def n_id(self) -> int:
+        return int(self.rev.shape[0])
+
+    def lengths(self) -> np.ndarray:
+        return (self.off[1:] - self.off[:-1]).astype(np.int64)
+
+    def truth_bitmask(self) -> np.ndarray:
+        return pack_bits(self.truth)
+
+    def block_ranges(self) -> list[tuple[int, int]]:
+        if self.block_sizes is None:
+            return [(0, self.n)]
+        ends = np.cumsum(self.block_sizes)
+        starts = ends - self.block_sizes
+        return [(int(a), int(b)) for a, b in zip(starts, ends)]
+
+
+def pack_bits(valid: np.ndarray) -> np.ndarray:
+    """bool[n] -> u32[ceil(n/32)]: bit i%32 of word i/32, LSB first, tail bits 0."""
+    n = valid.shape[0]
+    words = (n + 31) // 32
+    padded = np.zeros(words * 32, np.uint8)
+    padded[:n] = valid.astype(np.uint8)
+    by = np.packbits(padded.reshape(-1, 8), axis=1, bitorder="little").reshape(-1)
+    return by.view(np.uint32).copy() if words else np.zeros(0, np.uint32)
+
+
+def zipf_ids(rng_u: np.random.Generator, rng_perm: np.random.Generator, n: int, n_id: int,
+             s: float) -> np.ndarray:
+    """id = pi(rank), P(rank k) proportional to k^-s, inverse CDF on a float64 cumsum."""
+    w = np.arange(1, n_id + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    u = rng_u.random(n) * cdf[-1]
+    rank = np.minimum(np.searchsorted(cdf, u, side="right"), n_id - 1)
+    perm = rng_perm.permutation(n_id).astype(np.uint32)
+    return perm[rank]
+
+
+def lognormal_lengths(rng: np.random.Generator, n: int, median: float = 200.0,
+                      sigma: float = 0.75, lo: int = 64, hi: int = 1232) -> np.ndarray:
+    z = rng.standard_normal(n)
+    return np.clip(np.rint(np.exp(np.log(median) + sigma * z)), lo, hi).astype(np.int64)
+
+
+def generate(name: str, seed: int, n: int, n_id: int, lengths, id_dist: str = "uniform",
+             zipf_s: float = 1.1, n_invalid: int | None = None, p_invalid: float = 0.0,
+             kinds: Sequence[int] = (KIND_TAG, KIND_MSG), info: bytes = INFO_16,
+             block_sizes: np.ndarray | None = None, nthreads: int | None = None) -> Workload:
+    """Draw one workload.  ``lengths`` is an int, an int array, or a callable(rng, n)."""
+    ss = np.random.SeedSequence(seed)
+    (r_rev, r_salt, r_idu, r_perm, r_len, r_msg, r_bad, r_kind, r_bit,
+     r_wk) = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(10)]
+
+    rev = r_rev.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    salt = r_salt.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+
+    if id_dist == "uniform":
+        ids = r_idu.integers(0, n_id, size=n, dtype=np.uint32) if n_id else np.zeros(n, np.uint32)
+    elif id_dist == "zipf":
+        ids = zipf_ids(r_idu, r_perm, n, n_id, zipf_s)
+    else:
+        raise ValueError(id_dist)
+
+    if callable(lengths):
+        L = np.asarray(lengths(r_len, n), dtype=np.int64)
+    elif np.isscalar(lengths):
+        L = np.full(n, int(lengths), np.int64)
+    else:
+        L = np.asarray(lengths, dtype=np.int64)
+    off = np.zeros(n + 1, np.uint64)
+    np.cumsum(L, out=off[1:])
+    total = int(off[-1])
+    msg = r_msg.integers(0, 256, size=total, dtype=np.uint8)
+
+    if n_invalid is None:
+        n_invalid = int(np.floor(p_invalid * n + 0.5))
+    bad = r_bad.choice(n, size=n_invalid, replace=False) if n_invalid else np.zeros(0, np.int64)
+    kind = np.asarray(kinds, np.int64)[r_kind.integers(0, len(kinds), size=n_invalid)]
+    kind = np.where((kind == KIND_MSG) & (L[bad] == 0), KIND_TAG, kind)
+    kind = np.where((kind == KIND_KEY) & (n_id < 2), KIND_TAG, kind)
+
+    key_index = ids.copy()
+    wk = bad[kind == KIND_KEY]
+    if wk.size:
+        other = r_wk.integers(0, n_id - 1, size=wk.size, dtype=np.int64)
+        other = other + (other >= ids[wk])
+        key_index[wk] = other.astype(np.uint32)
+
+    keys = client_keys(rev, salt, info, nthreads)
+    tags = client_sign(keys, msg, off, key_index, nthreads)
+
+    # bit positions uniform within the chosen field
+    field_bits = np.where(kind == KIND_MSG, 8 * L[bad], 256)
+    bit = r_bit.integers(0, np.maximum(field_bits, 1), dtype=np.int64) if n_invalid else \
+        np.zeros(0, np.int64)
+    t_sel = kind == KIND_TAG
+    tb = bad[t_sel]
+    tags[tb, bit[t_sel] // 8] ^= (1 << (bit[t_sel] % 8)).astype(np.uint8)
+    m_sel = kind == KIND_MSG
+    mpos = off[bad[m_sel]].astype(np.int64) + bit[m_sel] // 8
+    np.bitwise_xor.at(msg, mpos, (1 << (bit[m_sel] % 8)).astype(np.uint8))
+
+    truth = np.ones(n, bool)
+    truth[bad] = False
+    meta = dict(seed=seed, n_invalid=int(n_invalid), kinds=list(map(int, kinds)),
+                id_dist=id_dist, bad=bad, bad_kind=kind)
+    return Workload(name, rev, salt, info, msg, off, ids.astype(np.uint32), tags, truth, keys,
+                    block_sizes, meta)
+
+
+# ----------------------------------------------------------------------------------------
+# The five workloads: tiny, block scale, throughput sweep, batching, serving pool.
+# ----------------------------------------------------------------------------------------
+SEED_BASE = 0xACE0
+
+
+def config1(nthreads=None) -> Workload:
+    """1,024 identities, 4,096 txs, uniform ids, 128-byte messages, 205 bad (tag/msg flips)."""
+    return generate("tiny", SEED_BASE + 1, n=4096, n_id=1024, lengths=128,
+                    n_invalid=int(np.floor(0.05 * 4096 + 0.5)), kinds=(KIND_TAG, KIND_MSG),
+                    nthreads=nthreads)
+
+
+def config2(nthreads=None) -> Workload:
+    """100,000 txs over 50,000 Zipf(1.1) identities, lengths U{96..512}, 1,000 bad."""
+    return generate("block", SEED_BASE + 2, n=100_000, n_id=50_000,
+                    lengths=lambda r, n: r.integers(96, 513, size=n),
+                    id_dist="zipf", n_invalid=1000, kinds=(KIND_TAG, KIND_MSG, KIND_KEY),
+                    nthreads=nthreads)
+
+
+def config3(n: int = 16 << 20, n_id: int = 1 << 20, id_dist: str = "uniform",
+            nthreads=None) -> Workload:
+    """Throughput sweep: n txs, 1M identities, lognormal(200, 0.75) lengths in [64, 1232]."""
+    return generate("sweep-%dM" % (n >> 20) if n >= (1 << 20) else "sweep-%d" % n,
+                    SEED_BASE + 3, n=n, n_id=n_id, lengths=lognormal_lengths, id_dist=id_dist,
+                    p_invalid=0.005, kinds=(KIND_TAG, KIND_MSG, KIND_KEY), nthreads=nthreads)
+
+
+def batching_block_sizes(n_blocks: int = 256, seed: int = SEED_BASE + 4) -> np.ndarray:
+    r = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))
+    z = r.standard_normal(n_blocks)
+    return np.clip(np.rint(np.exp(np.log(19_500.0) + 1.0 * z)), 1_000, 200_000).astype(np.int64)
+
+
+def config4(n_blocks: int = 256, n_id: int = 1 << 20, nthreads=None) -> Workload:
+    """256 blocks of lognormal(19,500, 1.0) sizes in [1k, 200k]; lengths as the sweep; Zipf ids."""
+    sizes = batching_block_sizes(n_blocks)
+    return generate("batching-%d" % n_blocks, SEED_BASE + 4, n=int(sizes.sum()), n_id=n_id,
+                    lengths=lognormal_lengths, id_dist="zipf", p_invalid=0.005,
+                    kinds=(KIND_TAG, KIND_MSG, KIND_KEY), block_sizes=sizes, nthreads=nthreads)
+
+
+def serving_request_sizes(n_req: int, seed: int = SEED_BASE + 5) -> np.ndarray:
+    r = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))
+    z = r.standard_normal(n_req)
+    return np.clip(np.rint(np.exp(np.log(1_000.0) + 1.5 * z)), 1, 50_000).astype(np.int64)
+
+
+def serving_arrivals(n_req: int, rate_hz: float, seed: int = SEED_BASE + 5) -> np.ndarray:
+    """Poisson arrivals: cumulative exponential gaps, seconds from t=0."""
+    r = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2])))
+    return np.cumsum(r.exponential(1.0 / rate_hz, size=n_req))
+
+
+def config5_pool(n_pool: int = 4 << 20, n_id: int = 4 << 20, nthreads=None) -> Workload:
+    """Transaction pool the serving requests are cut from: 4M Zipf identities, sweep lengths."""
+    return generate("serving-pool", SEED_BASE + 5, n=n_pool, n_id=n_id,
+                    lengths=lognormal_lengths, id_dist="zipf", p_invalid=0.005,
+                    kinds=(KIND_TAG, KIND_MSG, KIND_KEY), nthreads=nthreads)
+
+
+def subset(w: Workload, lo: int, hi: int, name: str | None = None) -> Workload:
+    """Transactions [lo, hi) of a workload as a workload of their own (messages copied)."""
+    a, b = int(w.off[lo]), int(w.off[hi])
+    off = (w.off[lo:hi + 1] - w.off[lo]).astype(np.uint64)
+    return Workload(name or "%s[%d:%d]" % (w.name, lo, hi), w.rev, w.salt, w.info,
+                    w.msg[a:b].copy(), off, w.ids[lo:hi].copy(), w.tags[lo:hi].copy(),
+                    w.truth[lo:hi].copy(), w.keys, None, dict(w.meta))

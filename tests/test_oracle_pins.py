@@ -1,0 +1,303 @@
+"""Pins of the CPU oracle against things other than itself.
+
+* SHA-256 / HMAC: Python's hashlib and hmac (OpenSSL) on seeded inputs,
+  every length that exercises a different padding case.
+* HKDF: the ``openssl kdf`` command line (RFC 5869 as OpenSSL implements it).
+* Constants: FIPS 180-4 sec. 4.2.2 / 5.3.3 closed forms, with exact integer
+  roots computed here in Python.
+* Midstates: HMAC through two single-block computations equals hashlib's HMAC.
+* Tamper invariants (Thm. attestation unforgeability): every single-bit flip
+  of root entropy, key, message or credential is rejected.
+* Context isolation (Def. 2.2): distinct salt or info gives distinct keys.
+* The generator's truth mask (its corruption plan) on the tiny and block-scale
+  workloads.
+"""
+import hashlib
+import hmac
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_10242_amd import workload as W
+
+
+def _rng(tag):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([0xACE0, tag])))
+
+
+def _bytes(r, n):
+    return r.integers(0, 256, size=n, dtype=np.uint8).tobytes()
+
+
+# ---------------------------------------------------------------- constants
+def _primes(k):
+    out, p = [], 2
+    while len(out) < k:
+        if all(p % q for q in out if q * q <= p):
+            out.append(p)
+        p += 1
+    return out
+
+
+def _icbrt(x):
+    lo, hi = 0, 1 << ((x.bit_length() + 2) // 3 + 1)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if mid ** 3 <= x:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def closed_form_constants():
+    import math
+    ps = _primes(64)
+    K = [(_icbrt(p << 96)) & 0xFFFFFFFF for p in ps]
+    IV = [math.isqrt(p << 64) & 0xFFFFFFFF for p in ps[:8]]
+    return np.array(K, np.uint32), np.array(IV, np.uint32)
+
+
+def test_constants_closed_form():
+    K, IV = oracle.constants()
+    Kc, IVc = closed_form_constants()
+    assert (K == Kc).all()
+    assert (IV == IVc).all()
+    # spot values that follow from the definition by hand: frac(sqrt 2) * 2^32
+    assert IV[0] == int((2 ** 0.5 - 1) * 2 ** 32)
+
+
+# ---------------------------------------------------------------- SHA-256
+def test_sha256_every_length_to_4096():
+    r = _rng(1)
+    data = _bytes(r, 4096)
+    for n in range(0, 4097):
+        assert oracle.sha256(data[:n]) == hashlib.sha256(data[:n]).digest(), n
+
+
+def test_sha256_large_random():
+    r = _rng(2)
+    for n in (65_537, 300_001, 1 << 20):
+        d = _bytes(r, n)
+        assert oracle.sha256(d) == hashlib.sha256(d).digest()
+
+
+def test_compress_is_one_block_of_sha256():
+    # F(H0, padded block) is SHA-256 of every message short enough for one block
+    r = _rng(3)
+    for n in range(0, 56):
+        m = _bytes(r, n)
+        blk = m + b"\x80" + b"\0" * (55 - n) + (8 * n).to_bytes(8, "big")
+        st = oracle.sha256_compress(oracle.sha256_iv(), blk)
+        assert st.astype(">u4").tobytes() == hashlib.sha256(m).digest()
+
+
+# ---------------------------------------------------------------- HMAC
+def test_hmac_key_lengths_0_to_200():
+    r = _rng(4)
+    msgs = [_bytes(r, n) for n in (0, 1, 40, 55, 56, 63, 64, 119, 120, 200, 1000, 2100)]
+    for klen in range(0, 201):
+        key = _bytes(r, klen)
+        for m in msgs:
+            assert oracle.hmac_sha256(key, m) == hmac.digest(key, m, "sha256"), (klen, len(m))
+
+
+def test_hmac_every_message_length_to_1300():
+    r = _rng(5)
+    key = _bytes(r, 32)
+    data = _bytes(r, 1300)
+    for n in range(0, 1301):
+        assert oracle.hmac_sha256(key, data[:n]) == hmac.digest(key, data[:n], "sha256"), n
+
+
+def test_hmac_through_midstates_equals_hmac():
+    # inner = F(ipad state, padded m) with bit length (64 + |m|) * 8,
+    # outer = F(opad state, padded inner) with bit length (64 + 32) * 8.
+    r = _rng(6)
+    keys = r.integers(0, 256, size=(16, 32), dtype=np.uint8)
+    mids = oracle.hmac_midstates(keys)
+    for j in range(16):
+        m = _bytes(r, 40)
+        blk = m + b"\x80" + b"\0" * 15 + ((64 + 40) * 8).to_bytes(8, "big")
+        inner = oracle.sha256_compress(mids[j, :8], blk).astype(">u4").tobytes()
+        blk2 = inner + b"\x80" + b"\0" * 23 + ((64 + 32) * 8).to_bytes(8, "big")
+        outer = oracle.sha256_compress(mids[j, 8:], blk2).astype(">u4").tobytes()
+        assert outer == hmac.digest(keys[j].tobytes(), m, "sha256")
+
+
+# ---------------------------------------------------------------- HKDF
+def _openssl_hkdf(salt, ikm, info, length):
+    cmd = ["openssl", "kdf", "-keylen", str(length), "-kdfopt", "digest:SHA256",
+           "-kdfopt", "hexkey:" + ikm.hex()]
+    if salt:
+        cmd += ["-kdfopt", "hexsalt:" + salt.hex()]
+    if info:
+        cmd += ["-kdfopt", "hexinfo:" + info.hex()]
+    out = subprocess.check_output(cmd + ["HKDF"], text=True).strip()
+    return bytes.fromhex(out.replace(":", ""))
+
+
+@pytest.mark.skipif(shutil.which("openssl") is None, reason="openssl CLI absent")
+def test_hkdf_against_openssl_cli():
+    r = _rng(7)
+    cases = []
+    for slen in (0, 1, 16, 32, 63, 64, 65, 80):
+        for ilen in (0, 1, 16, 23, 54, 55, 80):
+            cases.append((slen, ilen, 32))
+    cases += [(32, 16, L) for L in (1, 31, 33, 64, 100, 255, 1000, 255 * 32)]
+    for slen, ilen, L in cases:
+        salt, ikm, info = _bytes(r, slen), _bytes(r, 32), _bytes(r, ilen)
+        assert oracle.hkdf_sha256(salt, ikm, info, L) == _openssl_hkdf(salt, ikm, info, L), \
+            (slen, ilen, L)
+
+
+def test_hkdf_rejects_too_long_output():
+    with pytest.raises(ValueError):
+        oracle.hkdf_sha256(b"s", b"k", b"i", 255 * 32 + 1)
+
+
+def test_hkdf_paper_info_strings_against_openssl():
+    # the purpose strings named by Def. 2.1 and equation attestkey
+    info_lines = [l.split("\t")[1].encode() for l in
+                  open(__file__.replace("test_oracle_pins.py", "golden/info_strings.tsv"))
+                  .read().splitlines() if l and not l.startswith("#")]
+    r = _rng(8)
+    rev, salt = _bytes(r, 32), _bytes(r, 32)
+    keys = set()
+    for info in info_lines:
+        k = oracle.hkdf_sha256(salt, rev, info, 32)
+        if shutil.which("openssl"):
+            assert k == _openssl_hkdf(salt, rev, info, 32)
+        keys.add(k)
+    assert len(keys) == len(info_lines)
+
+
+def test_context_isolation_distinct_keys():
+    r = _rng(9)
+    rev = r.integers(0, 256, size=(64, 32), dtype=np.uint8)
+    a = oracle.derive_keys(rev, b"\x01" * 32, W.INFO_16)
+    b = oracle.derive_keys(rev, b"\x02" * 32, W.INFO_16)
+    c = oracle.derive_keys(rev, b"\x01" * 32, W.INFO_ATTEST)
+    all_keys = {bytes(k) for k in np.concatenate([a, b, c])}
+    assert len(all_keys) == 3 * 64
+
+
+# ---------------------------------------------------------------- batch verdicts
+def test_verify_matches_truth_tiny():
+    w = W.config1()
+    keys = oracle.derive_keys(w.rev, w.salt, w.info)
+    assert (keys == w.keys).all()          # oracle HKDF == OpenSSL HKDF, per identity
+    mask, count = oracle.verify_batch(keys, w.msg, w.off, w.ids, w.tags)
+    assert count == 4096 - 205 == int(w.truth.sum())
+    assert (mask == w.truth_bitmask()).all()
+
+
+def test_verify_matches_truth_block_scale():
+    w = W.config2()
+    mask, count = oracle.verify_batch_rev(w.rev, w.salt, w.info, w.msg, w.off, w.ids, w.tags,
+                                          nthreads=8)
+    assert count == 100_000 - 1000
+    assert (mask == w.truth_bitmask()).all()
+    m1, c1 = oracle.verify_batch(w.keys, w.msg, w.off, w.ids, w.tags, nthreads=1)
+    assert c1 == count and (m1 == mask).all()
+
+
+def test_verify_special_cases():
+    w = W.subset(W.config1(), 0, 100)
+    ids = w.ids.copy()
+    off = w.off.copy()
+    ids[3] = w.n_id                 # identity outside the registry
+    ids[4] = 0xFFFFFFFF
+    off[10], off[11] = off[11], off[10]  # tx 9 and 10 get decreasing offsets
+    mask, count = oracle.verify_batch(w.keys, w.msg, off, ids, w.tags)
+    truth = w.truth.copy()
+    truth[[3, 4]] = False
+    bits = np.unpackbits(mask.view(np.uint8), bitorder="little")[:100].astype(bool)
+    assert not bits[3] and not bits[4] and not bits[10]
+    for i in range(100):
+        if i in (3, 4, 9, 10, 11):
+            continue
+        assert bits[i] == truth[i]
+    # empty batch
+    m0, c0 = oracle.verify_batch(w.keys, w.msg[:0], np.zeros(1, np.uint64),
+                                 np.zeros(0, np.uint32), np.zeros((0, 32), np.uint8))
+    assert c0 == 0 and m0.size == 0
+
+
+def test_empty_message_is_verifiable():
+    key = bytes(range(32))
+    tag = np.frombuffer(hmac.digest(key, b"", "sha256"), np.uint8).reshape(1, 32)
+    mask, count = oracle.verify_batch(np.frombuffer(key, np.uint8).reshape(1, 32),
+                                      np.zeros(0, np.uint8), np.zeros(2, np.uint64),
+                                      np.zeros(1, np.uint32), tag)
+    assert count == 1 and mask[0] == 1
+
+
+def test_permuting_transactions_permutes_bits():
+    w = W.subset(W.config2(), 0, 3000)
+    r = _rng(10)
+    p = r.permutation(w.n)
+    L = w.lengths()[p]
+    off = np.zeros(w.n + 1, np.uint64)
+    np.cumsum(L, out=off[1:])
+    msg = np.concatenate([w.msg[int(w.off[i]):int(w.off[i + 1])] for i in p])
+    m0, c0 = oracle.verify_batch(w.keys, w.msg, w.off, w.ids, w.tags)
+    m1, c1 = oracle.verify_batch(w.keys, msg, off, w.ids[p], w.tags[p])
+    b0 = np.unpackbits(m0.view(np.uint8), bitorder="little")[: w.n]
+    b1 = np.unpackbits(m1.view(np.uint8), bitorder="little")[: w.n]
+    assert c0 == c1 and (b1 == b0[p]).all()
+
+
+# ---------------------------------------------------------------- tamper invariants
+def _paper_form_txs(count, seed):
+    """Messages of the paper's form m = obj_hash || domain (32 + 8 = 40 bytes)."""
+    r = _rng(seed)
+    rev = r.integers(0, 256, size=(count, 32), dtype=np.uint8)
+    salt = _bytes(r, 8)   # the domain c || s as an opaque 8-byte context
+    keys = W.client_keys(rev, salt, W.INFO_ATTEST)
+    msgs = [hashlib.sha256(_bytes(r, 200)).digest() + salt for _ in range(count)]
+    return rev, salt, keys, msgs
+
+
+def test_every_single_bit_flip_is_rejected():
+    rev, salt, keys, msgs = _paper_form_txs(64, 11)
+    ok_total = 0
+    for j in range(64):
+        key = keys[j].tobytes()
+        m = msgs[j]
+        tag = hmac.digest(key, m, "sha256")
+        variants_m, variants_t = [m], [tag]
+        for b in range(8 * len(m)):          # message flips
+            mm = bytearray(m); mm[b // 8] ^= 1 << (b % 8)
+            variants_m.append(bytes(mm)); variants_t.append(tag)
+        for b in range(256):                 # credential flips
+            tt = bytearray(tag); tt[b // 8] ^= 1 << (b % 8)
+            variants_m.append(m); variants_t.append(bytes(tt))
+        n = len(variants_m)
+        off = np.arange(n + 1, dtype=np.uint64) * 40
+        msg = np.frombuffer(b"".join(variants_m), np.uint8)
+        tags = np.frombuffer(b"".join(variants_t), np.uint8).reshape(n, 32)
+        mask, count = oracle.verify_batch(keys[j:j + 1], msg, off, np.zeros(n, np.uint32), tags)
+        bits = np.unpackbits(mask.view(np.uint8), bitorder="little")[:n]
+        assert bits[0] == 1 and count == 1, j
+        ok_total += count
+        # key flips: 256 flipped copies of the key, all checked against the true tag
+        kf = np.repeat(keys[j:j + 1], 256, axis=0)
+        kf[np.arange(256), np.arange(256) // 8] ^= (1 << (np.arange(256) % 8)).astype(np.uint8)
+        off1 = np.arange(257, dtype=np.uint64) * 40
+        mask, count = oracle.verify_batch(kf, np.frombuffer(m * 256, np.uint8), off1,
+                                          np.arange(256, dtype=np.uint32),
+                                          np.frombuffer(tag * 256, np.uint8).reshape(256, 32))
+        assert count == 0, j
+        # root-entropy flips: the derived key changes, so the credential fails
+        rf = np.repeat(rev[j:j + 1], 256, axis=0)
+        rf[np.arange(256), np.arange(256) // 8] ^= (1 << (np.arange(256) % 8)).astype(np.uint8)
+        mask, count = oracle.verify_batch_rev(rf, salt, W.INFO_ATTEST,
+                                              np.frombuffer(m * 256, np.uint8), off1,
+                                              np.arange(256, dtype=np.uint32),
+                                              np.frombuffer(tag * 256, np.uint8).reshape(256, 32))
+        assert count == 0, j
+    assert ok_total == 64
