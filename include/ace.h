@@ -1,0 +1,165 @@
+/*
+ * ace.h -- C ABI of libace.so: batched verification of HMAC-SHA256
+ * attestations under HKDF-SHA256 derived keys on one MI355X (gfx950).
+ *
+ * The operation is the attestation check of the ACE Runtime paper: Alg. 1,
+ * Phase 1a (AttestCheck) recomputes, for every transaction, the credential
+ * HMAC-SHA256(k, m) under the key of the transaction's identity and rejects
+ * the transaction when it differs from the attached credential; the key is
+ * k = HKDF-SHA256(REV, info, salt) (Def. 2.1, Def. 3.1 equation attestkey)
+ * and the credential is equation credential of Def. 3.1.  The message m is
+ * taken verbatim from the caller (the paper's m = obj_hash || domain is the
+ * 40-byte case); an identity index outside the registry is rejected (the
+ * identity existence check of Alg. 2).
+ *
+ * Conventions shared by every entry point:
+ *   - d_* arguments are HIP device pointers owned by the caller; h_* are host
+ *     pointers read before the call returns.  The library never frees or
+ *     retains caller memory and allocates no device memory: scratch space is
+ *     the caller's workspace.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously on it; outputs are valid once the stream has reached
+ *     the end of the call's work.
+ *   - A return value < 0 is an ace_status error.  Every argument error is
+ *     detected before anything is enqueued; ace_last_error() then describes
+ *     it (thread-local, valid until the next call on the same thread).
+ *   - An invalid transaction is data, not an error: a wrong credential, a
+ *     tampered message, a wrong key, an identity index >= n_id and an offset
+ *     pair with off[i+1] < off[i] all give bit 0.
+ *   - Bitmasks: bit i % 32 of 32-bit word i / 32 is transaction i (LSB
+ *     first); unused bits of the last word are 0.
+ *   - Midstates: for each identity, 16 native 32-bit words: words 0-7 are
+ *     the SHA-256 state after the block K0 ^ ipad, words 8-15 after K0 ^ opad
+ *     (RFC 2104 with B = 64; K0 = key || 32 zero bytes).
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACE_API __attribute__((visibility("default")))
+
+typedef enum {
+    ACE_OK = 0,
+    ACE_ERR_INVALID_ARG = -1, /* NULL where not allowed, bad length or flag */
+    ACE_ERR_RANGE = -2,       /* a count exceeds what the layout can index   */
+    ACE_ERR_NO_MEMORY = -3,   /* workspace or arena smaller than required    */
+    ACE_ERR_DEVICE = -4,      /* a HIP call failed                           */
+    ACE_ERR_AGAIN = -5,       /* non-blocking call: not done / no room yet   */
+    ACE_ERR_TOO_LARGE = -6    /* a request can never fit the arena           */
+} ace_status;
+
+/* Limits. */
+#define ACE_MAX_SALT_BYTES 1024u  /* HKDF salt; longer salts: ACE_ERR_INVALID_ARG */
+#define ACE_MAX_INFO_BYTES 255u   /* HKDF info                                  */
+#define ACE_MAX_TX 4294963200ull  /* 2^32 - 4096: total transactions per call   */
+
+/* Flags of ace_verify_batch. */
+#define ACE_ORDERED 0x1u    /* one transaction per lane in input order (no length bucketing) */
+#define ACE_BUCKETED 0x2u   /* group transactions by block count before hashing */
+#define ACE_PERSISTENT 0x4u /* fixed grid of workgroups pulling wave tiles from a counter */
+#define ACE_PER_TX_KEYS 0x8u /* keyset of kind ACE_KEYS_REV: derive each transaction's key
+                                inside the verify kernel instead of once per identity */
+/* Neither ORDERED nor BUCKETED: the library picks (bucketed for large batches). */
+
+/* Keyset kinds. */
+#define ACE_KEYS_MIDSTATE 0 /* d_mid[n_id][16]: cached HMAC midstates (from ace_derive_keys) */
+#define ACE_KEYS_REV 1      /* d_rev[n_id][32]: root entropy; keys derived in the call      */
+
+/* Last error detail of the calling thread ("" when none). */
+ACE_API const char *ace_last_error(void);
+/* Library version string. */
+ACE_API const char *ace_version(void);
+
+/*
+ * ace_derive_keys -- Def. 2.1 / equation attestkey, for n_id identities.
+ *   k_j = HKDF-SHA256(salt, IKM = REV_j, info, L = 32)        (RFC 5869)
+ * and, when d_mid_out is given, the HMAC midstates of k_j.
+ *   d_rev      [n_id][32] bytes, root entropy of each identity.
+ *   h_salt     salt_len bytes shared by all identities (the context; the
+ *              paper's domain).  salt_len 0 means HashLen zero bytes.
+ *              salt_len <= ACE_MAX_SALT_BYTES.
+ *   h_info     info_len bytes, info_len <= ACE_MAX_INFO_BYTES.
+ *   d_key_out  [n_id][32] bytes or NULL.
+ *   d_mid_out  [n_id][16] uint32 or NULL (not both NULL).
+ * n_id == 0 is a no-op.  Needs no workspace.
+ */
+ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *h_salt,
+                            size_t salt_len, const uint8_t *h_info, size_t info_len,
+                            uint8_t *d_key_out, uint32_t *d_mid_out, void *stream);
+
+/* One block of transactions (Alg. 1 SelectTransactions output). */
+typedef struct {
+    const uint8_t *d_msg;    /* messages back to back; may be NULL only if n_tx == 0      */
+    const uint64_t *d_off;   /* [n_tx + 1] byte offsets into d_msg; message i is
+                                d_msg[off[i] .. off[i+1]).  Offsets must lie within the
+                                message buffer (reading past it is undefined).           */
+    const uint32_t *d_id;    /* [n_tx] identity index into the keyset                     */
+    const uint8_t *d_tag;    /* [n_tx][32] credentials                                    */
+    uint64_t n_tx;
+    uint32_t *d_bitmask_out; /* [ceil(n_tx / 32)] words, fully written                    */
+    uint64_t *d_count_out;   /* one uint64: number of valid transactions                  */
+} ace_block;
+
+/* The identity registry the transactions refer to. */
+typedef struct {
+    int kind;                /* ACE_KEYS_MIDSTATE or ACE_KEYS_REV                           */
+    const uint32_t *d_mid;   /* kind MIDSTATE: [n_id][16]                                  */
+    const uint8_t *d_rev;    /* kind REV: [n_id][32]                                        */
+    uint32_t n_id;
+    const uint8_t *h_salt;   /* kind REV: HKDF salt and info as in ace_derive_keys          */
+    size_t salt_len;
+    const uint8_t *h_info;
+    size_t info_len;
+} ace_keyset;
+
+/* Workspace bytes ace_verify_batch needs for these arguments (0 on bad arguments). */
+ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,
+                                         uint32_t n_blocks, uint32_t flags);
+
+/*
+ * ace_verify_batch -- Alg. 1 Phase 1a over n_blocks blocks in one pass.
+ *   valid_i = (id_i < n_id) and (off_i <= off_{i+1}) and
+ *             HMAC-SHA256(k_{id_i}, msg_i) == tag_i (full 32-byte compare,
+ *             no early exit)
+ * Writes every block's bitmask and count.  All blocks are scheduled
+ * together, so many small blocks fill the GPU as one large one would.
+ *   d_workspace  device memory of at least ace_verify_workspace_size() bytes,
+ *                256-byte aligned; its content on entry is ignored.  It must
+ *                not be used by another call until this call's work is done.
+ *   flags        ACE_ORDERED / ACE_BUCKETED / ACE_PERSISTENT / ACE_PER_TX_KEYS.
+ * Sum of n_tx over blocks must be <= ACE_MAX_TX (else ACE_ERR_RANGE).
+ */
+ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+                             void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Stage timing (tracing).  While enabled on the calling thread, every
+ * ace_verify_batch call records HIP events on its own stream around its
+ * stages: key derivation, length binning (count, scan, scatter), the verify
+ * kernel and the finalize pass.  ace_profile_read() waits for the recorded
+ * events and returns the summed milliseconds of all profiled calls since the
+ * last reset (reset != 0 clears them).  Stages a call did not run add 0.
+ */
+typedef struct {
+    double derive_ms;
+    double bin_ms;
+    double verify_ms;
+    double finalize_ms;
+    double total_ms;
+    uint64_t calls;
+} ace_profile;
+
+ACE_API int ace_profile_enable(int on);
+ACE_API int ace_profile_read(ace_profile *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H */

@@ -1,0 +1,248 @@
+"""Python binding of ``libace.so`` (include/ace.h): argument marshalling only.
+
+Every step of the attestation check runs in the library's HIP kernels; this
+module passes torch-allocated device pointers and the current HIP stream.
+There is no fallback: if the library is missing or the GPU is absent, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime that libace.so then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libace.so")
+
+ACE_OK = 0
+ACE_ERR_INVALID_ARG = -1
+ACE_ERR_RANGE = -2
+ACE_ERR_NO_MEMORY = -3
+ACE_ERR_DEVICE = -4
+ACE_ERR_AGAIN = -5
+ACE_ERR_TOO_LARGE = -6
+
+ACE_ORDERED = 0x1
+ACE_BUCKETED = 0x2
+ACE_PERSISTENT = 0x4
+ACE_PER_TX_KEYS = 0x8
+
+ACE_KEYS_MIDSTATE = 0
+ACE_KEYS_REV = 1
+
+
+class AceError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("ace error %d: %s" % (code, msg))
+        self.code = code
+
+
+class ace_block(ctypes.Structure):
+    _fields_ = [("d_msg", ctypes.c_void_p), ("d_off", ctypes.c_void_p),
+                ("d_id", ctypes.c_void_p), ("d_tag", ctypes.c_void_p),
+                ("n_tx", ctypes.c_uint64), ("d_bitmask_out", ctypes.c_void_p),
+                ("d_count_out", ctypes.c_void_p)]
+
+
+class ace_keyset(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("d_mid", ctypes.c_void_p), ("d_rev", ctypes.c_void_p),
+                ("n_id", ctypes.c_uint32), ("h_salt", ctypes.c_void_p),
+                ("salt_len", ctypes.c_size_t), ("h_info", ctypes.c_void_p),
+                ("info_len", ctypes.c_size_t)]
+
+
+class ace_profile(ctypes.Structure):
+    _fields_ = [("derive_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
+                ("verify_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("calls", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libace.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libace.so not built (%s): run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, sz, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32
+    lib.ace_last_error.restype = ctypes.c_char_p
+    lib.ace_version.restype = ctypes.c_char_p
+    lib.ace_derive_keys.argtypes = [vp, u32, vp, sz, vp, sz, vp, vp, vp]
+    lib.ace_derive_keys.restype = ctypes.c_int
+    lib.ace_verify_workspace_size.argtypes = [ctypes.POINTER(ace_keyset),
+                                              ctypes.POINTER(ace_block), u32, u32]
+    lib.ace_verify_workspace_size.restype = sz
+    lib.ace_verify_batch.argtypes = [ctypes.POINTER(ace_keyset), ctypes.POINTER(ace_block), u32,
+                                     vp, sz, u32, vp]
+    lib.ace_verify_batch.restype = ctypes.c_int
+    lib.ace_profile_enable.argtypes = [ctypes.c_int]
+    lib.ace_profile_enable.restype = ctypes.c_int
+    lib.ace_profile_read.argtypes = [ctypes.POINTER(ace_profile), ctypes.c_int]
+    lib.ace_profile_read.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != ACE_OK:
+        raise AceError(rc, load().ace_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------------------ containers
+@dataclasses.dataclass
+class DeviceBlock:
+    """One block of transactions resident on the device, plus its outputs."""
+    msg: torch.Tensor       # uint8 [total bytes] (may be a shared buffer)
+    off: torch.Tensor       # int64 [n+1] (uint64 bits)
+    ids: torch.Tensor       # int32 [n]   (uint32 bits)
+    tags: torch.Tensor      # uint8 [n, 32]
+    bitmask: torch.Tensor   # int32 [ceil(n/32)]
+    count: torch.Tensor     # int64 [1]
+    n: int
+
+    def struct(self) -> ace_block:
+        return ace_block(_ptr(self.msg), _ptr(self.off),
+                         _ptr(self.ids), _ptr(self.tags), self.n, _ptr(self.bitmask),
+                         _ptr(self.count))
+
+    def result(self) -> tuple[np.ndarray, int]:
+        m = self.bitmask.cpu().numpy().view(np.uint32).copy()
+        return m, int(self.count.cpu().item())
+
+
+@dataclasses.dataclass
+class DeviceKeyset:
+    kind: int
+    n_id: int
+    mid: Optional[torch.Tensor] = None   # int32 [n_id, 16]
+    rev: Optional[torch.Tensor] = None   # uint8 [n_id, 32]
+    salt: bytes = b""
+    info: bytes = b""
+
+    def struct(self) -> tuple[ace_keyset, list]:
+        keep = [ctypes.create_string_buffer(self.salt, max(1, len(self.salt))),
+                ctypes.create_string_buffer(self.info, max(1, len(self.info)))]
+        ks = ace_keyset(self.kind, _ptr(self.mid), _ptr(self.rev), self.n_id,
+                        ctypes.addressof(keep[0]), len(self.salt), ctypes.addressof(keep[1]),
+                        len(self.info))
+        return ks, keep
+
+
+def to_device(a: np.ndarray, dtype=None, device="cuda") -> torch.Tensor:
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    elif a.dtype == np.uint32:
+        a = a.view(np.int32)
+    t = torch.from_numpy(a)
+    return t.to(device) if dtype is None else t.to(device=device, dtype=dtype)
+
+
+def upload_block(msg, off, ids, tags, device="cuda", msg_dev: Optional[torch.Tensor] = None
+                 ) -> DeviceBlock:
+    """Copies one block's arrays to the device and allocates its outputs."""
+    n = int(np.asarray(ids).shape[0])
+    if msg_dev is not None:
+        m = msg_dev
+    else:
+        host = np.asarray(msg, np.uint8).reshape(-1)
+        # an all-empty batch still gets a real (4-byte) buffer to point at
+        m = to_device(host if host.size else np.zeros(4, np.uint8), device=device)
+    return DeviceBlock(m, to_device(np.asarray(off, np.uint64), device=device),
+                       to_device(np.asarray(ids, np.uint32), device=device),
+                       to_device(np.asarray(tags, np.uint8).reshape(-1, 32), device=device),
+                       torch.zeros((n + 31) // 32, dtype=torch.int32, device=device),
+                       torch.zeros(1, dtype=torch.int64, device=device), n)
+
+
+# ------------------------------------------------------------------------------ entry points
+def derive_keys(rev: torch.Tensor, salt: bytes, info: bytes, key_out: Optional[torch.Tensor] = None,
+                mid_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """ace_derive_keys: HKDF-SHA256 keys and/or their HMAC midstates."""
+    n_id = int(rev.shape[0]) if rev is not None else 0
+    sb = ctypes.create_string_buffer(salt, max(1, len(salt)))
+    ib = ctypes.create_string_buffer(info, max(1, len(info)))
+    _check(load().ace_derive_keys(_ptr(rev) if n_id else None, n_id, ctypes.addressof(sb),
+                                  len(salt), ctypes.addressof(ib), len(info), _ptr(key_out),
+                                  _ptr(mid_out), _stream(stream)))
+
+
+def _blocks_array(blocks: Sequence[DeviceBlock]):
+    arr = (ace_block * max(1, len(blocks)))()
+    for i, b in enumerate(blocks):
+        arr[i] = b.struct()
+    return arr
+
+
+def verify_workspace_size(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock], flags: int = 0) -> int:
+    ks, keep = keyset.struct()
+    arr = _blocks_array(blocks)
+    return int(load().ace_verify_workspace_size(ctypes.byref(ks), arr, len(blocks), flags))
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def verify_batch(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
+                 ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """ace_verify_batch over the given blocks; returns the workspace used."""
+    ks, keep = keyset.struct()
+    arr = _blocks_array(blocks)
+    lib = load()
+    need = int(lib.ace_verify_workspace_size(ctypes.byref(ks), arr, len(blocks), flags))
+    if need == 0 and len(blocks):
+        _check(lib.ace_verify_batch(ctypes.byref(ks), arr, len(blocks), None, 0, flags, None))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, device=blocks[0].bitmask.device if blocks else "cuda")
+    _check(lib.ace_verify_batch(ctypes.byref(ks), arr, len(blocks), _ptr(ws), ws.numel(), flags,
+                                _stream(stream)))
+    return ws
+
+
+def midstate_keyset(rev: torch.Tensor, salt: bytes, info: bytes, stream=None) -> DeviceKeyset:
+    """Derives the resident midstate cache of a registry (ace_derive_keys)."""
+    n_id = int(rev.shape[0])
+    mid = torch.empty((max(n_id, 1), 16), dtype=torch.int32, device=rev.device)
+    if n_id:
+        derive_keys(rev, salt, info, mid_out=mid, stream=stream)
+    return DeviceKeyset(ACE_KEYS_MIDSTATE, n_id, mid=mid)
+
+
+def rev_keyset(rev: torch.Tensor, salt: bytes, info: bytes) -> DeviceKeyset:
+    return DeviceKeyset(ACE_KEYS_REV, int(rev.shape[0]), rev=rev, salt=salt, info=info)
+
+
+def profile_enable(on: bool = True) -> None:
+    """ace_profile_enable: stage timing of ace_verify_batch on this thread."""
+    _check(load().ace_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """ace_profile_read: summed stage milliseconds of the profiled calls."""
+    p = ace_profile()
+    _check(load().ace_profile_read(ctypes.byref(p), 1 if reset else 0))
+    return {k: getattr(p, k) for k, _ in ace_profile._fields_}

@@ -1,0 +1,422 @@
+// ace_api.hip -- host entry points of libace.so (declared in include/ace.h).
+//
+// Argument checking, workspace layout and the launch sequence.  Nothing here
+// computes any part of the attestation check: every hash runs in the kernels
+// of ace_kernels.hip.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ace.h"
+
+// The kernels are compiled in this translation unit.
+#include "ace_kernels.hip"
+
+using namespace ace;
+
+namespace {
+
+thread_local char g_err[512];
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return ACE_OK;
+    return fail(ACE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int launch_status(const char *what) { return check_hip(hipGetLastError(), what); }
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Compute units of the current device (cached per device).
+int cu_count()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+int fill_hkdf(HkdfParams &hp, const uint8_t *salt, size_t salt_len, const uint8_t *info,
+              size_t info_len)
+{
+    if (salt_len > kMaxSalt)
+        return fail(ACE_ERR_INVALID_ARG, "salt_len %zu exceeds %u", salt_len, kMaxSalt);
+    if (info_len > kMaxInfo)
+        return fail(ACE_ERR_INVALID_ARG, "info_len %zu exceeds %u", info_len, kMaxInfo);
+    if (salt_len && !salt) return fail(ACE_ERR_INVALID_ARG, "h_salt is NULL with salt_len > 0");
+    if (info_len && !info) return fail(ACE_ERR_INVALID_ARG, "h_info is NULL with info_len > 0");
+    memset(&hp, 0, sizeof hp);
+    hp.salt_len = (uint32_t)salt_len;
+    hp.info_len = (uint32_t)info_len;
+    if (salt_len) memcpy(hp.salt, salt, salt_len);
+    if (info_len) memcpy(hp.info, info, info_len);
+    return ACE_OK;
+}
+
+// Stage timing: one set of events per profiled call, reused after a reset.
+struct ProfCall {
+    hipEvent_t ev[5];  // start, after derive, after binning, after verify, end
+};
+struct ProfState {
+    bool on = false;
+    std::vector<ProfCall> calls;
+    size_t used = 0;
+    ~ProfState()
+    {
+        for (auto &c : calls)
+            for (auto &e : c.ev) hipEventDestroy(e);
+    }
+};
+thread_local ProfState g_prof;
+
+ProfCall *prof_begin(hipStream_t s)
+{
+    if (!g_prof.on) return nullptr;
+    if (g_prof.used == g_prof.calls.size()) {
+        ProfCall c;
+        for (auto &e : c.ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof.calls.push_back(c);
+    }
+    ProfCall *c = &g_prof.calls[g_prof.used++];
+    hipEventRecord(c->ev[0], s);
+    return c;
+}
+
+inline void prof_mark(ProfCall *c, int k, hipStream_t s)
+{
+    if (c) hipEventRecord(c->ev[k], s);
+}
+
+enum Mode { kOrdered, kBinned };
+
+// Batches at or above this many transactions are binned by length unless
+// the caller says otherwise.
+constexpr uint64_t kAutoBinnedMin = 1u << 18;
+
+struct Plan {
+    Mode mode;
+    bool per_tx;
+    bool persistent;
+    bool rev;
+    uint64_t total_tx;
+    uint64_t total_tiles;
+    uint64_t total_waves;
+    uint64_t max_pos;     // upper bound of bin-order positions
+    // workspace layout (byte offsets)
+    size_t off_ctrl, off_descs, off_mid, off_perm, off_posof, off_vperm, bytes;
+};
+
+int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks, uint32_t flags,
+              Plan &p)
+{
+    if (!keys) return fail(ACE_ERR_INVALID_ARG, "keys is NULL");
+    if (n_blocks && !blocks) return fail(ACE_ERR_INVALID_ARG, "blocks is NULL");
+    if (n_blocks >= (1u << 24)) return fail(ACE_ERR_RANGE, "n_blocks %u >= 2^24", n_blocks);
+    const uint32_t known = ACE_ORDERED | ACE_BUCKETED | ACE_PERSISTENT | ACE_PER_TX_KEYS;
+    if (flags & ~known) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
+    if ((flags & ACE_ORDERED) && (flags & ACE_BUCKETED))
+        return fail(ACE_ERR_INVALID_ARG, "ACE_ORDERED and ACE_BUCKETED are exclusive");
+    if (keys->kind != ACE_KEYS_MIDSTATE && keys->kind != ACE_KEYS_REV)
+        return fail(ACE_ERR_INVALID_ARG, "unknown keyset kind %d", keys->kind);
+    p.rev = keys->kind == ACE_KEYS_REV;
+    p.per_tx = (flags & ACE_PER_TX_KEYS) != 0;
+    if (p.per_tx && !p.rev) return fail(ACE_ERR_INVALID_ARG, "ACE_PER_TX_KEYS needs a keyset of kind ACE_KEYS_REV");
+    if (keys->n_id) {
+        if (p.rev) {
+            if (!keys->d_rev) return fail(ACE_ERR_INVALID_ARG, "keyset d_rev is NULL");
+            if (!aligned(keys->d_rev, 4)) return fail(ACE_ERR_INVALID_ARG, "keyset d_rev not 4-byte aligned");
+        } else {
+            if (!keys->d_mid) return fail(ACE_ERR_INVALID_ARG, "keyset d_mid is NULL");
+            if (!aligned(keys->d_mid, 16)) return fail(ACE_ERR_INVALID_ARG, "keyset d_mid not 16-byte aligned");
+        }
+    }
+    if (p.rev) {
+        if (keys->salt_len > kMaxSalt || keys->info_len > kMaxInfo)
+            return fail(ACE_ERR_INVALID_ARG, "salt_len or info_len too long");
+        if ((keys->salt_len && !keys->h_salt) || (keys->info_len && !keys->h_info))
+            return fail(ACE_ERR_INVALID_ARG, "keyset h_salt/h_info is NULL");
+    }
+    uint64_t total = 0, tiles = 0, waves = 0;
+    for (uint32_t b = 0; b < n_blocks; ++b) {
+        const ace_block &k = blocks[b];
+        if (!k.d_count_out) return fail(ACE_ERR_INVALID_ARG, "block %u: d_count_out is NULL", b);
+        if (!aligned(k.d_count_out, 8)) return fail(ACE_ERR_INVALID_ARG, "block %u: d_count_out not 8-byte aligned", b);
+        if (k.n_tx) {
+            if (!k.d_off || !k.d_id || !k.d_tag || !k.d_bitmask_out || !k.d_msg)
+                return fail(ACE_ERR_INVALID_ARG, "block %u: NULL array with n_tx > 0", b);
+            if (!aligned(k.d_off, 8) || !aligned(k.d_id, 4) || !aligned(k.d_tag, 4) ||
+                !aligned(k.d_bitmask_out, 4))
+                return fail(ACE_ERR_INVALID_ARG, "block %u: misaligned array", b);
+        }
+        if (k.n_tx > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "block %u: n_tx too large", b);
+        total += k.n_tx;
+        if (total > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "total transactions exceed ACE_MAX_TX");
+        tiles += (k.n_tx + kTile - 1) / kTile;
+        waves += (k.n_tx + 63) / 64;
+    }
+    p.total_tx = total;
+    p.total_tiles = tiles;
+    p.total_waves = waves;
+    if (flags & ACE_ORDERED) p.mode = kOrdered;
+    else if (flags & ACE_BUCKETED) p.mode = kBinned;
+    else p.mode = total >= kAutoBinnedMin ? kBinned : kOrdered;
+    p.persistent = (flags & ACE_PERSISTENT) != 0 && p.mode == kBinned;
+    p.max_pos = total + 64ull * kBins;
+
+    size_t o = 0;
+    p.off_ctrl = o;  o = align_up(o + sizeof(Ctrl), 256);
+    p.off_descs = o; o = align_up(o + (n_blocks > 1 ? n_blocks * sizeof(DevBlock) : 0), 256);
+    p.off_mid = o;   o = align_up(o + (p.rev && !p.per_tx ? 64ull * keys->n_id : 0), 256);
+    const bool binned = p.mode == kBinned;
+    p.off_perm = o;  o = align_up(o + (binned ? 8ull * p.max_pos : 0), 256);
+    p.off_posof = o; o = align_up(o + (binned ? 4ull * total : 0), 256);
+    p.off_vperm = o; o = align_up(o + (binned ? 4ull * (p.max_pos / 32 + 2) : 0), 256);
+    p.bytes = o;
+    return ACE_OK;
+}
+
+unsigned grid_for(uint64_t items, uint64_t per_wg, unsigned cap)
+{
+    uint64_t g = (items + per_wg - 1) / per_wg;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+extern "C" {
+
+ACE_API const char *ace_last_error(void) { return g_err; }
+
+ACE_API const char *ace_version(void) { return "ace 0.1 gfx950"; }
+
+ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *h_salt,
+                            size_t salt_len, const uint8_t *h_info, size_t info_len,
+                            uint8_t *d_key_out, uint32_t *d_mid_out, void *stream)
+{
+    clear_error();
+    if (!d_key_out && !d_mid_out) return fail(ACE_ERR_INVALID_ARG, "d_key_out and d_mid_out are both NULL");
+    HkdfParams hp;
+    int rc = fill_hkdf(hp, h_salt, salt_len, h_info, info_len);
+    if (rc) return rc;
+    if (n_id == 0) return ACE_OK;
+    if (!d_rev) return fail(ACE_ERR_INVALID_ARG, "d_rev is NULL");
+    if (!aligned(d_rev, 4) || (d_key_out && !aligned(d_key_out, 4)) || (d_mid_out && !aligned(d_mid_out, 4)))
+        return fail(ACE_ERR_INVALID_ARG, "misaligned device array");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const unsigned grid = (unsigned)((n_id + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_derive, dim3(grid), dim3(kWG), 0, s, d_rev, n_id, d_key_out, d_mid_out, hp);
+    return launch_status("k_derive launch");
+}
+
+ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,
+                                         uint32_t n_blocks, uint32_t flags)
+{
+    Plan p;
+    if (make_plan(keys, blocks, n_blocks, flags, p) != ACE_OK) return 0;
+    return p.bytes;
+}
+
+ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+                             void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream)
+{
+    clear_error();
+    Plan p;
+    int rc = make_plan(keys, blocks, n_blocks, flags, p);
+    if (rc) return rc;
+    if (n_blocks == 0) return ACE_OK;
+    if (!d_workspace) return fail(ACE_ERR_INVALID_ARG, "d_workspace is NULL");
+    if (!aligned(d_workspace, 256)) return fail(ACE_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
+    if (ws_bytes < p.bytes)
+        return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
+    HkdfParams hp;
+    memset(&hp, 0, sizeof hp);
+    if (p.rev) {
+        rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len);
+        if (rc) return rc;
+    }
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ProfCall *prof = prof_begin(s);
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+    DevBlock *table = reinterpret_cast<DevBlock *>(ws + p.off_descs);
+
+    // block descriptors with their prefixes
+    Batch bt;
+    memset(&bt, 0, sizeof bt);
+    bt.n_blocks = n_blocks;
+    bt.total_tx = p.total_tx;
+    bt.total_tiles = p.total_tiles;
+    bt.total_waves = p.total_waves;
+    {
+        DescChunk chunk;
+        memset(&chunk, 0, sizeof chunk);
+        uint64_t tx0 = 0, tile0 = 0, wave0 = 0;
+        for (uint32_t b = 0; b < n_blocks; ++b) {
+            const ace_block &k = blocks[b];
+            DevBlock d;
+            d.msg = k.d_msg;
+            d.off = k.d_off;
+            d.id = k.d_id;
+            d.tag = k.d_tag;
+            d.bitmask = k.d_bitmask_out;
+            d.count = reinterpret_cast<unsigned long long *>(k.d_count_out);
+            d.n = k.n_tx;
+            d.tx0 = tx0;
+            d.tile0 = tile0;
+            d.wave0 = wave0;
+            tx0 += k.n_tx;
+            tile0 += (k.n_tx + kTile - 1) / kTile;
+            wave0 += (k.n_tx + 63) / 64;
+            if (n_blocks == 1) {
+                bt.one = d;
+                break;
+            }
+            chunk.d[chunk.count++] = d;
+            if (chunk.count == kDescChunk || b + 1 == n_blocks) {
+                hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, table, chunk);
+                if ((rc = launch_status("k_put_descs launch"))) return rc;
+                chunk.first = b + 1;
+                chunk.count = 0;
+            }
+        }
+        bt.table = n_blocks > 1 ? table : nullptr;
+    }
+
+    KeySource ks;
+    ks.n_id = keys->n_id;
+    ks.mid = nullptr;
+    ks.rev = nullptr;
+    if (!p.rev) {
+        ks.mid = keys->d_mid;
+    } else if (p.per_tx) {
+        ks.rev = keys->d_rev;
+    } else {
+        uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
+        if (keys->n_id) {
+            const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
+            hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, s, keys->d_rev, keys->n_id,
+                               (uint8_t *)nullptr, mid, hp);
+            if ((rc = launch_status("k_derive launch"))) return rc;
+        }
+        ks.mid = mid;
+    }
+    prof_mark(prof, 1, s);
+
+    const bool binned = p.mode == kBinned;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n_blocks, kWG, 1024)), dim3(kWG), 0, s, bt,
+                       binned ? ctrl : (Ctrl *)nullptr);
+    if ((rc = launch_status("k_zero launch"))) return rc;
+    if (p.total_tx == 0 || !binned) {
+        prof_mark(prof, 2, s);
+        if (p.total_tx) {
+            const unsigned g = grid_for(p.total_waves, kWavesPerWG, 0x7fffffffu);
+            if (p.per_tx)
+                hipLaunchKernelGGL(k_verify_ordered<true>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+            else
+                hipLaunchKernelGGL(k_verify_ordered<false>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+            if ((rc = launch_status("k_verify_ordered launch"))) return rc;
+        }
+        prof_mark(prof, 3, s);
+        prof_mark(prof, 4, s);
+        return ACE_OK;
+    }
+
+    unsigned long long *perm = reinterpret_cast<unsigned long long *>(ws + p.off_perm);
+    uint32_t *pos_of = reinterpret_cast<uint32_t *>(ws + p.off_posof);
+    uint32_t *vperm = reinterpret_cast<uint32_t *>(ws + p.off_vperm);
+    const unsigned cus = (unsigned)cu_count();
+    const unsigned gtiles = grid_for(p.total_tiles, 1, 8 * cus);
+
+    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl);
+    if ((rc = launch_status("k_bin_count launch"))) return rc;
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
+    if ((rc = launch_status("k_bin_scan launch"))) return rc;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, perm, pos_of);
+    if ((rc = launch_status("k_bin_scatter launch"))) return rc;
+    prof_mark(prof, 2, s);
+
+    if (p.persistent) {
+        const unsigned g = 8 * cus;
+        if (p.per_tx)
+            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+        else
+            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+    } else {
+        const unsigned g = grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
+        if (p.per_tx)
+            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+        else
+            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+    }
+    if ((rc = launch_status("k_verify_binned launch"))) return rc;
+    prof_mark(prof, 3, s);
+    hipLaunchKernelGGL(k_finalize, dim3(gtiles), dim3(kWG), 0, s, bt, pos_of, vperm);
+    if ((rc = launch_status("k_finalize launch"))) return rc;
+    prof_mark(prof, 4, s);
+    return ACE_OK;
+}
+
+ACE_API int ace_profile_enable(int on)
+{
+    clear_error();
+    g_prof.on = on != 0;
+    return ACE_OK;
+}
+
+ACE_API int ace_profile_read(ace_profile *out, int reset)
+{
+    clear_error();
+    if (!out) return fail(ACE_ERR_INVALID_ARG, "out is NULL");
+    memset(out, 0, sizeof *out);
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        ProfCall &c = g_prof.calls[i];
+        float ms[4];
+        for (int k = 0; k < 4; ++k) {
+            int rc = check_hip(hipEventSynchronize(c.ev[k + 1]), "hipEventSynchronize");
+            if (rc) return rc;
+            rc = check_hip(hipEventElapsedTime(&ms[k], c.ev[k], c.ev[k + 1]), "hipEventElapsedTime");
+            if (rc) return rc;
+        }
+        out->derive_ms += ms[0];
+        out->bin_ms += ms[1];
+        out->verify_ms += ms[2];
+        out->finalize_ms += ms[3];
+        out->total_ms += ms[0] + ms[1] + ms[2] + ms[3];
+        out->calls += 1;
+    }
+    if (reset) g_prof.used = 0;
+    return ACE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// ace_internal.h -- device-side data layout shared by the kernels and the
+// host entry points of libace.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ace {
+
+constexpr int kWG = 256;          // threads per workgroup (4 wave64)
+constexpr int kWavesPerWG = kWG / 64;
+constexpr int kTile = 2048;       // transactions per tile of the binning/finalize passes
+constexpr int kBins = 64;         // bins by inner block count nb = ceil((L+9)/64); bin 63 = nb >= 64
+constexpr uint32_t kMaxSalt = 1024;
+constexpr uint32_t kMaxInfo = 255;
+constexpr uint32_t kMaxInfoBlocks = 5;  // ceil((64 + 255 + 1 + 9) / 64) - 1
+
+// One block of transactions as the kernels see it, plus its prefixes in the
+// concatenated index spaces of a multi-block call.
+struct DevBlock {
+    const uint8_t *msg;
+    const uint64_t *off;
+    const uint32_t *id;
+    const uint8_t *tag;
+    uint32_t *bitmask;
+    unsigned long long *count;
+    uint64_t n;      // transactions
+    uint64_t tx0;    // first global transaction index
+    uint64_t tile0;  // first tile (kTile transactions per tile)
+    uint64_t wave0;  // first wave tile of the in-order verify (64 per wave)
+};
+
+// Blocks of one call: a single block travels inline in the kernel arguments,
+// several blocks in a device table.
+struct Batch {
+    DevBlock one;
+    const DevBlock *table;
+    uint32_t n_blocks;
+    uint64_t total_tx;
+    uint64_t total_tiles;
+    uint64_t total_waves;
+};
+
+// Control words of a bucketed pass (start of the workspace).
+struct Ctrl {
+    uint32_t hist[kBins];    // transactions per bin
+    uint32_t cursor[kBins];  // next free position per bin (scatter)
+    uint32_t ostart[kBins];  // bins in order o = 63 - bin (longest first): padded start
+    uint32_t ocount[kBins];  // real transactions
+    uint32_t opad[kBins];    // count rounded up to a multiple of 64
+    uint32_t total_pos;      // sum of opad
+    uint32_t work;           // wave-tile counter of the persistent verify
+    uint32_t pad_[62];
+};
+
+// HKDF parameters shared by all identities of a keyset (kernel argument).
+struct HkdfParams {
+    uint32_t salt_len;
+    uint32_t info_len;
+    uint8_t salt[kMaxSalt];
+    uint8_t info[kMaxInfo + 1];
+};
+
+// Derived per-workgroup constants of an HKDF parameter set (built in LDS).
+struct HkdfPrep {
+    uint32_t salt_ipad[8];
+    uint32_t salt_opad[8];
+    uint32_t info_words[kMaxInfoBlocks][16];
+    uint32_t info_blocks;
+};
+
+struct KeySource {
+    const uint32_t *mid;   // [n_id][16] midstates, or NULL when keys come from rev
+    const uint8_t *rev;    // [n_id][32] root entropy (per-transaction derivation)
+    uint32_t n_id;
+};
+
+// A chunk of block descriptors passed by value to the kernel that writes
+// them into the device table (no host staging buffer is needed).
+constexpr int kDescChunk = 24;
+struct DescChunk {
+    DevBlock d[kDescChunk];
+    uint32_t first;
+    uint32_t count;
+};
+
+__host__ __device__ inline uint32_t bin_of_length(uint64_t L)
+{
+    uint64_t nb = (L + 9 + 63) >> 6;
+    return (uint32_t)(nb >= (uint64_t)kBins ? kBins : nb) - 1u;
+}
+
+}  // namespace ace

@@ -1,0 +1,639 @@
+// ace_kernels.hip -- gfx950 kernels of the attestation check.
+//
+//   k_derive         HKDF-SHA256 per identity (Def. 2.1 / equation attestkey)
+//                    and the HMAC midstates of the derived key.
+//   k_zero           clears the per-block counts and the binning control words.
+//   k_bin_count      histogram of transactions by inner block count.
+//   k_bin_scan       bin start positions, longest messages first.
+//   k_bin_scatter    transaction indices into bin order.
+//   k_verify         Alg. 1 Phase 1a per transaction: inner hash of the message
+//                    from the cached ipad midstate, outer hash from the opad
+//                    midstate, constant-time compare with the credential,
+//                    wave64 ballot of the verdicts.
+//   k_finalize       bin-order verdicts back to input order; per-block counts.
+//
+// One transaction per lane.  Message bytes are read straight from HBM as
+// aligned dwords and turned into big-endian schedule words with one
+// v_perm_b32 each, whose per-lane selector also absorbs the message's byte
+// misalignment; the padding (0x80, zeros, bit length) is applied on the fly
+// in the last one or two blocks of each message.
+#include "ace_internal.h"
+#include "sha256_gfx950.h"
+
+namespace ace {
+
+// ------------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// 16-byte load from a 4-byte aligned address.
+__device__ __forceinline__ U4 load16(const uint32_t *p)
+{
+    U4 v;
+    __builtin_memcpy(&v, p, 16);
+    return v;
+}
+
+__device__ __forceinline__ DevBlock get_block(const Batch &bt, uint32_t b)
+{
+    if (bt.n_blocks == 1) return bt.one;
+    return bt.table[b];
+}
+
+// Last block whose prefix (selected by `field`) is <= x; empty blocks share
+// their prefix with the next block, so the last match is the owner.
+template <int FIELD>
+__device__ __forceinline__ uint32_t find_block(const Batch &bt, uint64_t x)
+{
+    if (bt.n_blocks == 1) return 0;
+    uint32_t lo = 0, hi = bt.n_blocks;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const DevBlock &d = bt.table[mid];
+        const uint64_t v = FIELD == 0 ? d.tile0 : d.wave0;
+        if (v <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Big-endian word g of the SHA-256 padding of the byte string
+// p[0..len) || tail[0..tail_len) whose bit-length field holds `bitlen` and
+// whose padded form has `nblocks` blocks (FIPS 180-4 sec. 5.1.1).
+__device__ inline uint32_t padded_word(const uint8_t *p, uint32_t len, uint32_t tail,
+                                       uint32_t tail_len, uint32_t g, uint32_t nblocks,
+                                       uint64_t bitlen)
+{
+    if (g == 16 * nblocks - 2) return (uint32_t)(bitlen >> 32);
+    if (g == 16 * nblocks - 1) return (uint32_t)bitlen;
+    const uint32_t total = len + tail_len;
+    uint32_t w = 0;
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t pos = 4 * g + k;
+        uint32_t byte;
+        if (pos < len) byte = p[pos];
+        else if (pos < total) byte = (tail >> (8 * (pos - len))) & 0xFFu;
+        else byte = pos == total ? 0x80u : 0u;
+        w = (w << 8) | byte;
+    }
+    return w;
+}
+
+// Per-workgroup HKDF constants: the salt's HMAC midstates and the padded
+// expand input (info || 0x01), built by wave 0 (all lanes compute the same
+// values) into LDS.
+__device__ void hkdf_prepare(const HkdfParams &hp, HkdfPrep &out)
+{
+    uint32_t k0[16];
+    const uint32_t sl = hp.salt_len;
+    if (sl > 64) {
+        // RFC 2104: keys longer than the block are hashed first.
+        const uint32_t nblk = (sl + 9 + 63) / 64;
+        State s = initial_state();
+        for (uint32_t blk = 0; blk < nblk; ++blk) {
+            uint32_t W[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W[j] = padded_word(hp.salt, sl, 0, 0, 16 * blk + j, nblk, 8ull * sl);
+            compress(s, W);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) k0[j] = s.h[j];
+#pragma unroll
+        for (int j = 8; j < 16; ++j) k0[j] = 0;
+    } else {
+        // RFC 5869: an absent salt is HashLen zero bytes, whose key block is
+        // the same all-zero K0 as the empty key's.
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            uint32_t w = 0;
+            for (uint32_t k = 0; k < 4; ++k) {
+                const uint32_t pos = 4 * j + k;
+                w = (w << 8) | (pos < sl ? hp.salt[pos] : 0u);
+            }
+            k0[j] = w;
+        }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint32_t x = pass ? 0x5c5c5c5cu : 0x36363636u;
+        uint32_t W[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) W[j] = k0[j] ^ x;
+        State s = initial_state();
+        compress(s, W);
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) (pass ? out.salt_opad : out.salt_ipad)[j] = s.h[j];
+        }
+    }
+    // Expand input T(1) = HMAC(PRK, info || 0x01): after the 64-byte key
+    // block the hashed stream is info || 0x01, bit length (64 + len + 1) * 8.
+    const uint32_t il = hp.info_len;
+    const uint32_t nq = (il + 1 + 9 + 63) / 64;
+    if (lane_id() == 0) {
+        for (uint32_t q = 0; q < nq; ++q)
+            for (uint32_t j = 0; j < 16; ++j)
+                out.info_words[q][j] =
+                    padded_word(hp.info, il, 0x01u, 1, 16 * q + j, nq, 8ull * (64 + il + 1));
+        out.info_blocks = nq;
+    }
+}
+
+// HKDF-SHA256 (RFC 5869, L = 32) of one 32-byte root entropy rv (big-endian
+// words) and the midstates of the resulting key, as one loop over a single
+// compression body (keeps the code small enough for the instruction cache):
+//   0 inner extract   F(salt_ipad, rv || pad)
+//   1 PRK             F(salt_opad, inner || pad)
+//   2,3               PRK midstates F(IV, PRK^ipad), F(IV, PRK^opad)
+//   4 .. 3+nq         expand inner over info || 0x01 from the PRK ipad state
+//   4+nq  key k       F(PRK opad state, inner || pad)
+//   5+nq, 6+nq        key midstates F(IV, k^ipad), F(IV, k^opad)
+__device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], const HkdfPrep &P,
+                                            uint32_t (&key)[8], State &kip, State &kop)
+{
+    const uint32_t nq = P.info_blocks;
+    const uint32_t nsteps = 7 + nq;
+    State x, A, B;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { x.h[i] = 0; A.h[i] = 0; B.h[i] = 0; }
+    for (uint32_t s = 0; s < nsteps; ++s) {
+        uint32_t W[16];
+        State in;
+        if (s == 0 || s == 1 || s == 4 + nq) {
+            // 32-byte message after a key block: words 8..15 are fixed
+            if (s == 0) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) { in.h[i] = P.salt_ipad[i]; W[i] = rv[i]; }
+            } else if (s == 1) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) { in.h[i] = P.salt_opad[i]; W[i] = x.h[i]; }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) { in.h[i] = A.h[i]; W[i] = x.h[i]; }
+            }
+            W[8] = 0x80000000u;
+#pragma unroll
+            for (int i = 9; i < 15; ++i) W[i] = 0;
+            W[15] = 768u;
+        } else if (s == 2 || s == 3 || s == 5 + nq || s == 6 + nq) {
+            // key midstates: the key is A (PRK or k) after the move below
+            if (s == 2 || s == 5 + nq) A = x;
+            else B = x;
+            const uint32_t pad = (s == 2 || s == 5 + nq) ? 0x36363636u : 0x5c5c5c5cu;
+            in = initial_state();
+#pragma unroll
+            for (int i = 0; i < 8; ++i) W[i] = A.h[i] ^ pad;
+#pragma unroll
+            for (int i = 8; i < 16; ++i) W[i] = pad;
+        } else {
+            // expand blocks: first one starts from the PRK ipad state (B)
+            if (s == 4) {
+                const State pi = B;
+                A = x;   // PRK opad state, needed at step 4 + nq
+                in = pi;
+            } else {
+                in = x;
+            }
+            const uint32_t q = s - 4;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
+        }
+        if (live) compress(in, W);
+        x = in;
+    }
+    // after the loop: A = k, B = F(IV, k^ipad), x = F(IV, k^opad)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) key[i] = A.h[i];
+    kip = B;
+    kop = x;
+}
+
+// ------------------------------------------------------------------------------------------
+// k_derive: one identity per lane.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
+                                                uint8_t *__restrict__ key_out,
+                                                uint32_t *__restrict__ mid_out, HkdfParams hp)
+{
+    __shared__ HkdfPrep prep;
+    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
+    __syncthreads();
+
+    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
+    const bool live = j < n_id;
+    uint32_t rv[8];
+    if (live) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(rev + 32ull * j);
+        const U4 a = load16(p), b = load16(p + 4);
+        rv[0] = bswap32(a.x); rv[1] = bswap32(a.y); rv[2] = bswap32(a.z); rv[3] = bswap32(a.w);
+        rv[4] = bswap32(b.x); rv[5] = bswap32(b.y); rv[6] = bswap32(b.z); rv[7] = bswap32(b.w);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rv[i] = 0;
+    }
+    uint32_t key[8];
+    State kip, kop;
+    derive_lane(live, rv, prep, key, kip, kop);
+    if (!live) return;
+    if (key_out) {
+        uint32_t *q = reinterpret_cast<uint32_t *>(key_out + 32ull * j);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q[i] = bswap32(key[i]);
+    }
+    if (mid_out) {
+        uint32_t *q = mid_out + 16ull * j;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) { q[i] = kip.h[i]; q[8 + i] = kop.h[i]; }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Verification of one transaction per lane.
+// ------------------------------------------------------------------------------------------
+struct TxRef {
+    const uint8_t *msg;   // message start
+    uint64_t L;           // message length
+    const uint32_t *mid;  // midstate row (ipad 0..7, opad 8..15), if cached
+    const uint8_t *rev;   // root entropy row, if derived per transaction
+    const uint8_t *tag;   // credential
+};
+
+template <bool PER_TX_KEYS>
+__device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const HkdfPrep *prep)
+{
+    State S, opad;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { S.h[i] = 0; opad.h[i] = 0; }
+    if constexpr (PER_TX_KEYS) {
+        uint32_t rv[8];
+        if (live) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(t.rev);
+            const U4 a = load16(p), b = load16(p + 4);
+            rv[0] = bswap32(a.x); rv[1] = bswap32(a.y); rv[2] = bswap32(a.z); rv[3] = bswap32(a.w);
+            rv[4] = bswap32(b.x); rv[5] = bswap32(b.y); rv[6] = bswap32(b.z); rv[7] = bswap32(b.w);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) rv[i] = 0;
+        }
+        uint32_t key[8];
+        derive_lane(live, rv, *prep, key, S, opad);
+    } else {
+        if (live) {
+            const U4 a = load16(t.mid), b = load16(t.mid + 4);
+            S.h[0] = a.x; S.h[1] = a.y; S.h[2] = a.z; S.h[3] = a.w;
+            S.h[4] = b.x; S.h[5] = b.y; S.h[6] = b.z; S.h[7] = b.w;
+        }
+    }
+
+    const uint64_t L = t.L;
+    const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;  // inner blocks
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(t.msg);
+    const uint32_t sh = (uint32_t)addr & 3u;
+    const uint32_t sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
+    const uint64_t lim = (uint64_t)sh + L;                  // dword k holds message bytes iff 4k < lim
+    const uint64_t last = lim ? ((lim - 1) >> 2) : 0;
+    // every load address is clamped to a dword that holds message bytes (or,
+    // for an empty message, to the credential): nothing outside the
+    // caller's buffers is touched, and clamped values only feed bytes the
+    // padding overwrites.
+    const uint32_t *A0 = lim ? reinterpret_cast<const uint32_t *>(addr - sh)
+                             : reinterpret_cast<const uint32_t *>(t.tag);
+    const uint32_t len_hi = (uint32_t)((64 + L) >> 29);
+    const uint32_t len_lo = (uint32_t)((64 + L) << 3);
+
+    for (uint32_t b = 0;; ++b) {
+        const bool run = live && b <= nb;
+        if (__ballot(run) == 0) break;
+        if (run) {
+            uint32_t W[16];
+            State in;
+            if (b < nb) {
+                in = S;
+                const uint64_t g0 = 16ull * b;
+                const int64_t rb = (int64_t)L - 64 * (int64_t)b;  // message bytes from this block on
+                uint32_t D[17];
+                if (rb >= 64) {
+                    const uint32_t *q = A0 + g0;
+                    const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
+                    D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
+                    D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
+                    D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
+                    D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
+                    const uint64_t k16 = g0 + 16;
+                    D[16] = A0[k16 < last ? k16 : last];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 17; ++k) {
+                        const uint64_t idx = g0 + k;
+                        D[k] = A0[idx < last ? idx : last];
+                    }
+                    const int32_t r0 = (int32_t)rb;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int32_t r = r0 - 4 * j;  // message bytes left at word j
+                        const uint32_t wf = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+                        const uint32_t s8 = ((uint32_t)r & 3u) << 3;
+                        const uint32_t part = (wf & ~(0xFFFFFFFFu >> s8)) | (0x80000000u >> s8);
+                        W[j] = r >= 4 ? wf : (r >= 0 ? part : 0u);
+                    }
+                    if (b + 1 == nb) {
+                        W[14] = len_hi;
+                        W[15] = len_lo;
+                    }
+                }
+            } else {
+                // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
+                if constexpr (PER_TX_KEYS) {
+                    in = opad;
+                } else {
+                    const U4 a = load16(t.mid + 8), c = load16(t.mid + 12);
+                    in.h[0] = a.x; in.h[1] = a.y; in.h[2] = a.z; in.h[3] = a.w;
+                    in.h[4] = c.x; in.h[5] = c.y; in.h[6] = c.z; in.h[7] = c.w;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) W[i] = S.h[i];
+                W[8] = 0x80000000u;
+#pragma unroll
+                for (int i = 9; i < 15; ++i) W[i] = 0u;
+                W[15] = 768u;
+            }
+            compress(in, W);
+            S = in;
+        }
+    }
+
+    bool ok = false;
+    if (live) {
+        const uint32_t *tp = reinterpret_cast<const uint32_t *>(t.tag);
+        const U4 a = load16(tp), c = load16(tp + 4);
+        uint32_t d = 0;
+        d = or_xor(d, S.h[0], bswap32(a.x)); d = or_xor(d, S.h[1], bswap32(a.y));
+        d = or_xor(d, S.h[2], bswap32(a.z)); d = or_xor(d, S.h[3], bswap32(a.w));
+        d = or_xor(d, S.h[4], bswap32(c.x)); d = or_xor(d, S.h[5], bswap32(c.y));
+        d = or_xor(d, S.h[6], bswap32(c.z)); d = or_xor(d, S.h[7], bswap32(c.w));
+        ok = d == 0;
+    }
+    return ok;
+}
+
+// Loads what one lane needs about transaction i of block d.  Returns whether
+// the transaction can be valid at all (registered identity, ordered offsets).
+__device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const KeySource &ks, TxRef &t)
+{
+    const uint64_t a = d.off[i], e = d.off[i + 1];
+    const uint32_t who = d.id[i];
+    const bool ok = who < ks.n_id && a <= e;
+    t.msg = d.msg + a;
+    t.L = ok ? e - a : 0;
+    t.mid = ks.mid ? ks.mid + 16ull * (ok ? who : 0u) : nullptr;
+    t.rev = ks.rev ? ks.rev + 32ull * (ok ? who : 0u) : nullptr;
+    t.tag = d.tag + 32ull * i;
+    return ok;
+}
+
+// ------------------------------------------------------------------------------------------
+// k_verify, in-order form: wave tile w covers transactions 64w' .. 64w'+63 of
+// one block; the ballot is that block's two bitmask words.
+// ------------------------------------------------------------------------------------------
+template <bool PER_TX_KEYS>
+__global__ void __launch_bounds__(kWG) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
+{
+    __shared__ HkdfPrep prep;
+    if constexpr (PER_TX_KEYS) {
+        if (threadIdx.x < 64) hkdf_prepare(hp, prep);
+        __syncthreads();
+    }
+    const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
+    if (w >= bt.total_waves) return;
+    const uint32_t b = find_block<1>(bt, w);
+    const DevBlock d = get_block(bt, b);
+    const uint64_t i0 = 64ull * (w - d.wave0);
+    const uint64_t i = i0 + lane_id();
+    const bool active = i < d.n;
+    TxRef t{};
+    bool live = false;
+    if (active) live = load_tx(d, i, ks, t);
+    const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
+    const unsigned long long m = __ballot(valid);
+    if (lane_id() == 0) {
+        d.bitmask[i0 >> 5] = (uint32_t)m;
+        if (i0 + 32 < d.n) d.bitmask[(i0 >> 5) + 1] = (uint32_t)(m >> 32);
+        const unsigned c = __popcll(m);
+        if (c) atomicAdd(d.count, (unsigned long long)c);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Binning by inner block count.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
+{
+    const uint32_t t = blockIdx.x * kWG + threadIdx.x;
+    for (uint32_t b = t; b < bt.n_blocks; b += gridDim.x * kWG) *get_block(bt, b).count = 0;
+    if (ctrl && blockIdx.x == 0 && threadIdx.x < kBins) {
+        ctrl->hist[threadIdx.x] = 0;
+        ctrl->cursor[threadIdx.x] = 0;
+        if (threadIdx.x == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
+    }
+}
+
+__device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i)
+{
+    const uint64_t a = d.off[i], e = d.off[i + 1];
+    return a <= e ? e - a : 0;
+}
+
+__global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl)
+{
+    __shared__ uint32_t h[kBins];
+    if (threadIdx.x < kBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
+        const DevBlock d = get_block(bt, find_block<0>(bt, tile));
+        const uint64_t i0 = (tile - d.tile0) * kTile;
+        for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
+            const uint64_t i = i0 + k;
+            if (i < d.n) atomicAdd(&h[bin_of_length(tx_length(d, i))], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins && h[threadIdx.x]) atomicAdd(&ctrl->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// One wave: bins laid out longest first so the longest waves start first.
+__global__ void k_bin_scan(Ctrl *ctrl)
+{
+    const uint32_t o = threadIdx.x;          // order position
+    const uint32_t bin = kBins - 1 - o;
+    const uint32_t cnt = ctrl->hist[bin];
+    const uint32_t pad = (cnt + 63u) & ~63u;
+    __shared__ uint32_t s[kBins];
+    s[o] = pad;
+    __syncthreads();
+    uint32_t start = 0;
+    for (uint32_t k = 0; k < o; ++k) start += s[k];
+    ctrl->ostart[o] = start;
+    ctrl->ocount[o] = cnt;
+    ctrl->opad[o] = pad;
+    ctrl->cursor[bin] = start;
+    if (o == kBins - 1) ctrl->total_pos = start + pad;
+}
+
+__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
+                                                     unsigned long long *__restrict__ perm,
+                                                     uint32_t *__restrict__ pos_of)
+{
+    constexpr int kPer = kTile / kWG;
+    __shared__ uint32_t cnt[kBins];
+    __shared__ uint32_t base[kBins];
+    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
+        const uint32_t b = find_block<0>(bt, tile);
+        const DevBlock d = get_block(bt, b);
+        const uint64_t i0 = (tile - d.tile0) * kTile;
+        if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t bins[kPer], rank[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+            bins[k] = kBins;
+            if (i < d.n) {
+                bins[k] = bin_of_length(tx_length(d, i));
+                rank[k] = atomicAdd(&cnt[bins[k]], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kBins && cnt[threadIdx.x])
+            base[threadIdx.x] = atomicAdd(&ctrl->cursor[threadIdx.x], cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (bins[k] < kBins) {
+                const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+                const uint32_t pos = base[bins[k]] + rank[k];
+                perm[pos] = ((unsigned long long)b << 40) | i;
+                pos_of[d.tx0 + i] = pos;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// k_verify, binned form: wave tile w covers bin-order positions 64w..64w+63,
+// all in one bin; verdicts go to a bin-order bitmap.
+// ------------------------------------------------------------------------------------------
+template <bool PER_TX_KEYS, bool PERSISTENT>
+__global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
+                                                       Ctrl *ctrl,
+                                                       const unsigned long long *__restrict__ perm,
+                                                       uint32_t *__restrict__ vperm)
+{
+    __shared__ HkdfPrep prep;
+    __shared__ uint32_t ostart[kBins], ocount[kBins], oend[kBins];
+    if constexpr (PER_TX_KEYS) {
+        if (threadIdx.x < 64) hkdf_prepare(hp, prep);
+    }
+    if (threadIdx.x < kBins) {
+        ostart[threadIdx.x] = ctrl->ostart[threadIdx.x];
+        ocount[threadIdx.x] = ctrl->ocount[threadIdx.x];
+        oend[threadIdx.x] = ctrl->ostart[threadIdx.x] + ctrl->opad[threadIdx.x];
+    }
+    __syncthreads();
+    const uint32_t total = ctrl->total_pos;
+    const uint32_t nwaves = total >> 6;
+    const uint32_t lane = lane_id();
+    uint32_t w = PERSISTENT ? 0u : blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
+    for (;;) {
+        if constexpr (PERSISTENT) {
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(&ctrl->work, 1u);
+            w = __builtin_amdgcn_readfirstlane(v);
+        }
+        if (w >= nwaves) break;
+        const uint32_t k0 = w << 6;
+        // bin of this wave: number of bins that end at or before k0
+        const uint32_t o = __popcll(__ballot(oend[lane] <= k0));
+        const uint32_t k = k0 + lane;
+        const bool active = k - ostart[o] < ocount[o];
+        TxRef t{};
+        bool live = false;
+        if (active) {
+            const unsigned long long e = perm[k];
+            const uint32_t b = (uint32_t)(e >> 40);
+            const uint64_t i = e & ((1ull << 40) - 1);
+            const DevBlock d = get_block(bt, b);
+            live = load_tx(d, i, ks, t);
+        }
+        const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
+        const unsigned long long m = __ballot(valid);
+        if (lane == 0) {
+            vperm[2 * w] = (uint32_t)m;
+            vperm[2 * w + 1] = (uint32_t)(m >> 32);
+        }
+        if constexpr (!PERSISTENT) break;
+    }
+}
+
+// Bin-order verdicts back to input order: one lane per transaction, wave64
+// ballot per 64 transactions, one count atomic per workgroup and block.
+__global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__restrict__ pos_of,
+                                                  const uint32_t *__restrict__ vperm)
+{
+    __shared__ unsigned long long part[kWavesPerWG];
+    const uint32_t lane = lane_id();
+    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
+        const DevBlock d = get_block(bt, find_block<0>(bt, tile));
+        const uint64_t i0 = (tile - d.tile0) * kTile;
+        unsigned long long acc = 0;
+        for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
+            const uint64_t i = i0 + k;
+            bool bit = false;
+            if (i < d.n) {
+                const uint32_t p = pos_of[d.tx0 + i];
+                bit = (vperm[p >> 5] >> (p & 31)) & 1u;
+            }
+            const unsigned long long m = __ballot(bit);
+            const uint64_t base = i - lane;
+            if (lane == 0 && base < d.n) {
+                d.bitmask[base >> 5] = (uint32_t)m;
+                if (base + 32 < d.n) d.bitmask[(base >> 5) + 1] = (uint32_t)(m >> 32);
+            }
+            acc += __popcll(m);
+        }
+        if (lane == 0) part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long s = 0;
+            for (int v = 0; v < kWavesPerWG; ++v) s += part[v];
+            if (s) atomicAdd(d.count, s);
+        }
+        __syncthreads();
+    }
+}
+
+// Writes a chunk of block descriptors (passed by value) into the device table.
+__global__ void k_put_descs(DevBlock *table, DescChunk c)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < c.count) table[c.first + t] = c.d[t];
+}
+
+// Explicit instantiations used by the host entry points.
+template __global__ void k_verify_ordered<false>(Batch, KeySource, HkdfParams);
+template __global__ void k_verify_ordered<true>(Batch, KeySource, HkdfParams);
+template __global__ void k_verify_binned<false, false>(Batch, KeySource, HkdfParams, Ctrl *,
+                                                       const unsigned long long *, uint32_t *);
+template __global__ void k_verify_binned<false, true>(Batch, KeySource, HkdfParams, Ctrl *,
+                                                      const unsigned long long *, uint32_t *);
+template __global__ void k_verify_binned<true, false>(Batch, KeySource, HkdfParams, Ctrl *,
+                                                      const unsigned long long *, uint32_t *);
+template __global__ void k_verify_binned<true, true>(Batch, KeySource, HkdfParams, Ctrl *,
+                                                     const unsigned long long *, uint32_t *);
+
+}  // namespace ace

@@ -1,0 +1,139 @@
+"""Host-only checks of libace.so: it loads, exports every entry point that
+include/ace.h declares, rejects malformed calls before touching the GPU, and
+its SHA-256 constant table equals the FIPS 180-4 closed form."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.test_oracle_pins import closed_form_constants
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ace.h")
+DEVICE_SHA = os.path.join(ROOT, "paper_2603_10242_amd", "csrc", "sha256_gfx950.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"ACE_API\s+[^;(]*?\b(ace_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2603_10242_amd import ace
+    return ace.load()
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for name in ("ace_derive_keys", "ace_verify_batch", "ace_verify_workspace_size",
+                 "ace_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_device_constants_equal_closed_form():
+    text = open(DEVICE_SHA).read()
+    body = text[text.index("kRound[64]"):]
+    k = [int(x, 16) for x in re.findall(r"0x([0-9a-f]{8})u", body[: body.index("};")])]
+    body = text[text.index("kInit[8]"):]
+    iv = [int(x, 16) for x in re.findall(r"0x([0-9a-f]{8})u", body[: body.index("};")])]
+    K, IV = closed_form_constants()
+    assert k == list(map(int, K)) and iv == list(map(int, IV))
+
+
+def _keyset(ace, kind=0, n_id=4, mid=0x1000, rev=0, salt=b"", info=b""):
+    sb = ctypes.create_string_buffer(salt or b"\0")
+    ib = ctypes.create_string_buffer(info or b"\0")
+    ks = ace.ace_keyset(kind, mid or None, rev or None, n_id, ctypes.addressof(sb), len(salt),
+                        ctypes.addressof(ib), len(info))
+    return ks, (sb, ib)
+
+
+def _block(ace, n=100, **kw):
+    f = dict(d_msg=0x10000, d_off=0x20000, d_id=0x30000, d_tag=0x40000, n_tx=n,
+             d_bitmask_out=0x50000, d_count_out=0x60000)
+    f.update(kw)
+    return ace.ace_block(*[f[k] for k, _ in ace.ace_block._fields_])
+
+
+def test_argument_errors_are_reported_before_any_launch(lib):
+    from paper_2603_10242_amd import ace
+    ks, keep = _keyset(ace)
+    blk = (ace.ace_block * 1)(_block(ace))
+    # no workspace
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, None, 0, 0, None) == ace.ACE_ERR_INVALID_ARG
+    assert b"workspace" in lib.ace_last_error()
+    # workspace too small
+    need = lib.ace_verify_workspace_size(ctypes.byref(ks), blk, 1, 0)
+    assert need > 0
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, 0x100000, need - 256, 0,
+                                None) == ace.ACE_ERR_NO_MEMORY
+    # misaligned workspace
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, 0x100010, need, 0,
+                                None) == ace.ACE_ERR_INVALID_ARG
+    # exclusive flags, unknown flags
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, 0x100000, need,
+                                ace.ACE_ORDERED | ace.ACE_BUCKETED, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, 0x100000, need, 0x100,
+                                None) == ace.ACE_ERR_INVALID_ARG
+    # per-transaction keys need root entropy
+    assert lib.ace_verify_batch(ctypes.byref(ks), blk, 1, 0x100000, need, ace.ACE_PER_TX_KEYS,
+                                None) == ace.ACE_ERR_INVALID_ARG
+    # NULL arrays, misaligned arrays, NULL count
+    for bad in (dict(d_off=0), dict(d_tag=0), dict(d_id=0x30001), dict(d_count_out=0),
+                dict(d_off=0x20004)):
+        b = (ace.ace_block * 1)(_block(ace, **bad))
+        assert lib.ace_verify_batch(ctypes.byref(ks), b, 1, 0x100000, need, 0,
+                                    None) == ace.ACE_ERR_INVALID_ARG, bad
+    # too many transactions
+    b = (ace.ace_block * 2)(_block(ace, n=1 << 31), _block(ace, n=1 << 31))
+    assert lib.ace_verify_batch(ctypes.byref(ks), b, 2, 0x100000, need, 0,
+                                None) == ace.ACE_ERR_RANGE
+    # unknown keyset kind, missing keyset pointers
+    ks2, k2 = _keyset(ace, kind=7)
+    assert lib.ace_verify_batch(ctypes.byref(ks2), blk, 1, 0x100000, need, 0,
+                                None) == ace.ACE_ERR_INVALID_ARG
+    ks3, k3 = _keyset(ace, kind=1, rev=0)
+    assert lib.ace_verify_batch(ctypes.byref(ks3), blk, 1, 0x100000, need, 0,
+                                None) == ace.ACE_ERR_INVALID_ARG
+    ks4, k4 = _keyset(ace, kind=1, rev=0x7000, salt=b"x" * 1025)
+    assert lib.ace_verify_batch(ctypes.byref(ks4), blk, 1, 0x100000, need, 0,
+                                None) == ace.ACE_ERR_INVALID_ARG
+
+
+def test_derive_argument_errors(lib):
+    from paper_2603_10242_amd import ace
+    salt = ctypes.create_string_buffer(b"s" * 32)
+    info = ctypes.create_string_buffer(b"i" * 300)
+    # both outputs NULL
+    assert lib.ace_derive_keys(0x1000, 4, salt, 32, info, 16, None, None, None) == ace.ACE_ERR_INVALID_ARG
+    # info too long, salt too long
+    assert lib.ace_derive_keys(0x1000, 4, salt, 32, info, 256, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_derive_keys(0x1000, 4, salt, 1025, info, 16, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    # NULL root entropy
+    assert lib.ace_derive_keys(None, 4, salt, 32, info, 16, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    # zero identities is a no-op that never launches
+    assert lib.ace_derive_keys(None, 0, salt, 32, info, 16, 0x2000, None, None) == ace.ACE_OK
+
+
+def test_workspace_size_layout(lib):
+    from paper_2603_10242_amd import ace
+    ks, keep = _keyset(ace)
+    one = (ace.ace_block * 1)(_block(ace, n=1_000_000))
+    ordered = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_ORDERED)
+    binned = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_BUCKETED)
+    assert 0 < ordered < 4096
+    # binned: 8 B permutation + 4 B position + 1 bit per transaction, plus padding
+    assert binned >= ordered + 12 * 1_000_000
+    assert binned < ordered + 13 * 1_000_000 + 64 * 1024
+    rks, rkeep = _keyset(ace, kind=1, rev=0x7000, n_id=1000)
+    with_mid = lib.ace_verify_workspace_size(ctypes.byref(rks), one, 1, ace.ACE_ORDERED)
+    assert with_mid >= ordered + 64 * 1000
+    assert lib.ace_verify_workspace_size(None, one, 1, 0) == 0

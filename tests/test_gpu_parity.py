@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle and with the
+generator's truth mask.  Integer work: every bitmask word and count must be
+identical (tolerance 0)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_10242_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = {
+    "ordered": 0x1,
+    "binned": 0x2,
+    "binned-persistent": 0x2 | 0x4,
+}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ace(need_gpu):
+    import torch
+    from paper_2603_10242_amd import ace as A
+    A.load()
+    torch.cuda.set_device(0)
+    return A
+
+
+def oracle_result(w, keys=None, nthreads=8, ids=None, off=None):
+    keys = oracle.derive_keys(w.rev, w.salt, w.info, nthreads) if keys is None else keys
+    return oracle.verify_batch(keys, w.msg, w.off if off is None else off,
+                               w.ids if ids is None else ids, w.tags, nthreads)
+
+
+def run(ace, w, keyset, flags, ids=None, off=None):
+    import torch
+    blk = ace.upload_block(w.msg, w.off if off is None else off, w.ids if ids is None else ids,
+                           w.tags)
+    ace.verify_batch(keyset, [blk], flags=flags)
+    torch.cuda.synchronize()
+    return blk.result()
+
+
+def keysets(ace, w):
+    rev = ace.to_device(w.rev)
+    return {
+        "midstate": ace.midstate_keyset(rev, w.salt, w.info),
+        "rev": ace.rev_keyset(rev, w.salt, w.info),
+    }
+
+
+# ------------------------------------------------------------------ key derivation
+@pytest.mark.parametrize("salt_len", [0, 1, 32, 64, 65, 200, 1024])
+def test_derive_keys_salts(ace, salt_len):
+    import torch
+    note("derive_keys salt_len=%d" % salt_len)
+    r = np.random.Generator(np.random.PCG64(salt_len + 7))
+    n_id = 1000
+    rev = r.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    salt = r.integers(0, 256, size=salt_len, dtype=np.uint8).tobytes()
+    info = W.INFO_16
+    d_rev = ace.to_device(rev)
+    key = torch.zeros((n_id, 32), dtype=torch.uint8, device="cuda")
+    mid = torch.zeros((n_id, 16), dtype=torch.int32, device="cuda")
+    ace.derive_keys(d_rev, salt, info, key_out=key, mid_out=mid)
+    torch.cuda.synchronize()
+    okeys = oracle.derive_keys(rev, salt, info, 8)
+    assert np.array_equal(key.cpu().numpy(), okeys)
+    assert np.array_equal(mid.cpu().numpy().view(np.uint32), oracle.hmac_midstates(okeys))
+
+
+@pytest.mark.parametrize("info", [b"", W.INFO_16, W.INFO_ATTEST, b"x" * 54, b"y" * 55,
+                                  b"z" * 100, bytes(range(255))])
+def test_derive_keys_infos(ace, info):
+    import torch
+    note("derive_keys info_len=%d" % len(info))
+    r = np.random.Generator(np.random.PCG64(len(info) + 100))
+    n_id = 333
+    rev = r.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    salt = r.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+    key = torch.zeros((n_id, 32), dtype=torch.uint8, device="cuda")
+    ace.derive_keys(ace.to_device(rev), salt, info, key_out=key)
+    torch.cuda.synchronize()
+    assert np.array_equal(key.cpu().numpy(), oracle.derive_keys(rev, salt, info, 8))
+
+
+def test_derive_keys_match_openssl_client_keys(ace):
+    import torch
+    w = W.config1()
+    key = torch.zeros((w.n_id, 32), dtype=torch.uint8, device="cuda")
+    ace.derive_keys(ace.to_device(w.rev), w.salt, w.info, key_out=key)
+    torch.cuda.synchronize()
+    assert np.array_equal(key.cpu().numpy(), w.keys)
+
+
+# ------------------------------------------------------------------ the tiny and block workloads
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("keys", ["midstate", "rev", "rev-per-tx"])
+def test_tiny(ace, mode, keys):
+    note("tiny mode=%s keys=%s" % (mode, keys))
+    w = W.config1()
+    ks = keysets(ace, w)["rev" if keys.startswith("rev") else "midstate"]
+    flags = MODES[mode] | (0x8 if keys == "rev-per-tx" else 0)
+    mask, count = run(ace, w, ks, flags)
+    omask, ocount = oracle_result(w, keys=w.keys)
+    assert count == ocount == 4096 - 205
+    assert np.array_equal(mask, omask)
+    assert np.array_equal(mask, w.truth_bitmask())
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_block_scale_keys_in_launch(ace, mode):
+    note("block scale mode=%s" % mode)
+    w = W.config2()
+    mask, count = run(ace, w, keysets(ace, w)["rev"], MODES[mode])
+    omask, ocount = oracle_result(w)
+    assert count == ocount == 99_000
+    assert np.array_equal(mask, omask)
+    assert np.array_equal(mask, w.truth_bitmask())
+
+
+def test_block_scale_per_tx_keys(ace):
+    w = W.config2()
+    mask, count = run(ace, w, keysets(ace, w)["rev"], MODES["binned"] | 0x8)
+    assert count == 99_000 and np.array_equal(mask, w.truth_bitmask())
+
+
+# ------------------------------------------------------------------ every padding case
+@pytest.mark.parametrize("mode", list(MODES))
+def test_every_length_0_to_1300_misaligned(ace, mode):
+    """Every message length 0..1300 (each padding case), groups of 100 messages
+    behind a random 0-3 byte lead so messages start at every alignment."""
+    import torch
+    note("lengths 0..1300 mode=%s" % mode)
+    L = np.arange(0, 1301, dtype=np.int64)
+    r = np.random.Generator(np.random.PCG64(1301))
+    n_id = 64
+    rev = r.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    salt = r.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+    keys = W.client_keys(rev, salt, W.INFO_16)
+    ids = r.integers(0, n_id, size=L.size).astype(np.uint32)
+    blocks, cases = [], []
+    for lo in range(0, L.size, 100):
+        hi = min(L.size, lo + 100)
+        lead = int(r.integers(0, 4))
+        off = np.zeros(hi - lo + 1, np.uint64)
+        np.cumsum(L[lo:hi], out=off[1:])
+        off += lead
+        buf = r.integers(0, 256, size=int(off[-1]) + 1, dtype=np.uint8)[: int(off[-1])]
+        tags = W.client_sign(keys, buf, off, ids[lo:hi])
+        truth = np.ones(hi - lo, bool)
+        flip = r.random(hi - lo) < 0.1
+        tags[flip, 0] ^= 1
+        truth[flip] = False
+        blocks.append(ace.upload_block(buf, off, ids[lo:hi], tags))
+        cases.append((truth, buf, off, ids[lo:hi], tags))
+    ks = ace.midstate_keyset(ace.to_device(rev), salt, W.INFO_16)
+    ace.verify_batch(ks, blocks, flags=MODES[mode])
+    torch.cuda.synchronize()
+    for blk, (truth, buf, off, ids_b, tags) in zip(blocks, cases):
+        mask, count = blk.result()
+        omask, ocount = oracle.verify_batch(keys, buf, off, ids_b, tags)
+        assert count == ocount == int(truth.sum())
+        assert np.array_equal(mask, omask)
+        assert np.array_equal(mask, W.pack_bits(truth))
+
+
+def test_long_messages_catch_all_bin(ace):
+    import torch
+    note("long messages")
+    lengths = [4000, 4023, 4024, 4096, 5000, 9000, 20000, 63, 64, 1232] * 7
+    w = W.generate("long", 99, n=len(lengths), n_id=16, lengths=np.array(lengths),
+                   n_invalid=7, kinds=(W.KIND_TAG, W.KIND_MSG, W.KIND_KEY))
+    for mode in MODES.values():
+        mask, count = run(ace, w, keysets(ace, w)["midstate"], mode)
+        assert count == w.n - 7 and np.array_equal(mask, w.truth_bitmask())
+
+
+# ------------------------------------------------------------------ batch shapes, edge cases
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 63, 64, 65, 4097])
+def test_batch_sizes(ace, n):
+    note("batch size n=%d" % n)
+    base = W.config2()
+    w = W.subset(base, 0, n)
+    ks = keysets(ace, w)
+    for mode in MODES.values():
+        for name in ("midstate", "rev"):
+            mask, count = run(ace, w, ks[name], mode)
+            assert count == int(w.truth.sum())
+            assert mask.shape[0] == (n + 31) // 32
+            assert np.array_equal(mask, w.truth_bitmask())
+
+
+def test_unregistered_ids_and_bad_offsets(ace):
+    note("unregistered ids, decreasing offsets")
+    w = W.subset(W.config2(), 0, 5000)
+    ids = w.ids.copy()
+    off = w.off.copy()
+    ids[[3, 100, 4999]] = [w.n_id, 0xFFFFFFFF, w.n_id + 5]
+    off[200], off[201] = off[201], off[200]
+    omask, ocount = oracle_result(w, ids=ids, off=off)
+    for mode in MODES.values():
+        for name, ks in keysets(ace, w).items():
+            mask, count = run(ace, w, ks, mode, ids=ids, off=off)
+            assert count == ocount and np.array_equal(mask, omask), (mode, name)
+
+
+def test_all_valid_and_all_invalid(ace):
+    w = W.generate("clean", 5, n=3000, n_id=100, lengths=lambda r, n: r.integers(0, 700, size=n))
+    for mode in MODES.values():
+        mask, count = run(ace, w, keysets(ace, w)["midstate"], mode)
+        assert count == 3000 and np.array_equal(mask, w.truth_bitmask())
+    bad = W.generate("dirty", 6, n=3000, n_id=100, lengths=lambda r, n: r.integers(0, 700, size=n),
+                     n_invalid=3000, kinds=(W.KIND_TAG, W.KIND_MSG, W.KIND_KEY))
+    for mode in MODES.values():
+        mask, count = run(ace, bad, keysets(ace, bad)["rev"], mode)
+        assert count == 0 and not mask.any()
+
+
+def test_empty_registry(ace):
+    import torch
+    w = W.subset(W.config1(), 0, 100)
+    empty = ace.DeviceKeyset(ace.ACE_KEYS_MIDSTATE, 0,
+                             mid=torch.zeros((1, 16), dtype=torch.int32, device="cuda"))
+    for mode in MODES.values():
+        mask, count = run(ace, w, empty, mode)
+        assert count == 0 and not mask.any()
+
+
+# ------------------------------------------------------------------ several blocks in one call
+@pytest.mark.parametrize("mode", list(MODES))
+def test_multi_block(ace, mode):
+    import torch
+    note("multi-block mode=%s" % mode)
+    w = W.config2()
+    sizes = [0, 1, 100, 3000, 64, 65, 5000, 0, 2048, 31, 20000, 7]
+    ks = keysets(ace, w)["rev"]
+    d_msg = ace.to_device(w.msg)
+    blocks, parts = [], []
+    lo = 0
+    for s in sizes:
+        hi = lo + s
+        # every block addresses the shared message buffer with absolute offsets
+        blocks.append(ace.upload_block(None, w.off[lo:hi + 1], w.ids[lo:hi], w.tags[lo:hi],
+                                       msg_dev=d_msg))
+        parts.append((lo, hi))
+        lo = hi
+    ace.verify_batch(ks, blocks, flags=MODES[mode])
+    torch.cuda.synchronize()
+    for blk, (lo, hi) in zip(blocks, parts):
+        mask, count = blk.result()
+        truth = w.truth[lo:hi]
+        assert count == int(truth.sum()), (lo, hi)
+        assert np.array_equal(mask, W.pack_bits(truth)), (lo, hi)
+
+
+def test_many_blocks_256(ace):
+    import torch
+    note("256 blocks")
+    w = W.subset(W.config2(), 0, 60_000)
+    r = np.random.Generator(np.random.PCG64(256))
+    cuts = np.sort(r.choice(np.arange(1, w.n), size=255, replace=False))
+    edges = np.concatenate([[0], cuts, [w.n]])
+    d_msg = ace.to_device(w.msg)
+    blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
+              for a, b in zip(edges[:-1], edges[1:])]
+    for mode in MODES.values():
+        ace.verify_batch(keysets(ace, w)["midstate"], blocks, flags=mode)
+        torch.cuda.synchronize()
+        for blk, a, b in zip(blocks, edges[:-1], edges[1:]):
+            mask, count = blk.result()
+            assert count == int(w.truth[a:b].sum())
+            assert np.array_equal(mask, W.pack_bits(w.truth[a:b]))
