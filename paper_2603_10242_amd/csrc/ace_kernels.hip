@@ -551,8 +551,11 @@ __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, H
     uint32_t w = PERSISTENT ? 0u : blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
     for (;;) {
         if constexpr (PERSISTENT) {
-            uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(&ctrl->work, 1u);
+            // Every lane takes part in the atomic (lane 0 adds 1, the others 0)
+            // so no divergent branch precedes the readfirstlane: with the
+            // atomic under `if (lane == 0)` the compiler may split this loop
+            // per lane and leave lanes 1..63 re-reading a stale tile forever.
+            const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? 1u : 0u);
             w = __builtin_amdgcn_readfirstlane(v);
         }
         if (w >= nwaves) break;
@@ -591,8 +594,9 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
         const DevBlock d = get_block(bt, find_block<0>(bt, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
         unsigned long long acc = 0;
-        for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
-            const uint64_t i = i0 + k;
+#pragma unroll
+        for (int it = 0; it < kTile / kWG; ++it) {  // uniform trip count: the ballot sees every lane
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)it * kWG;
             bool bit = false;
             if (i < d.n) {
                 const uint32_t p = pos_of[d.tx0 + i];
