@@ -69,6 +69,91 @@ def cpu_baseline(w, seconds: float) -> dict:
                       (w.n_id, t_derive, sample, w.n, t_verify)}
 
 
+def time_calls(fn, steps: int, warmup: int):
+    """Per-call wall times (ms) of fn() bracketed by stream events, after warmup."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        fn()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    return wall * 1e3 / steps, ev
+
+
+def bench_batching(args) -> dict:
+    """256 blocks of lognormal sizes in one captured replay, against one eager
+    multi-block call and against one plain call per block."""
+    from paper_2603_10242_amd import workload as W
+    log("generating the batching workload (256 blocks)")
+    w = W.config4()
+    import torch
+    from paper_2603_10242_amd import ace
+    ace.load()
+    torch.cuda.set_device(0)
+    edges = np.concatenate([[0], np.cumsum(w.block_sizes)])
+    d_msg = ace.to_device(w.msg)
+    blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
+              for a, b in zip(edges[:-1], edges[1:])]
+    ks = ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info)
+    L = w.lengths()
+    comp = compressions(L)
+    g = ace.Graph(ks, max_blocks=len(blocks), max_tx=w.n)
+    ws_multi = ace.workspace(ace.verify_workspace_size(ks, blocks, 0))
+    ws_one = ace.workspace(max(ace.verify_workspace_size(ks, [b], 0) for b in blocks))
+    torch.cuda.synchronize()
+    log("uploaded %d txs in %d blocks (%.3f compressions/tx)" % (w.n, len(blocks), comp / w.n))
+
+    def check(tag):
+        for blk, a, b in zip(blocks, edges[:-1], edges[1:]):
+            m, c = blk.result()
+            if c != int(w.truth[a:b].sum()) or not np.array_equal(m, W.pack_bits(w.truth[a:b])):
+                raise SystemExit("RESULT MISMATCH in %s" % tag)
+
+    forms = {
+        "graph": lambda: g.launch(blocks),
+        "multi_block_call": lambda: ace.verify_batch(ks, blocks, ws_multi, 0),
+        "per_block_calls": lambda: [ace.verify_batch(ks, [b], ws_one, 0) for b in blocks],
+    }
+    out = {}
+    for name, fn in forms.items():
+        fn()
+        torch.cuda.synchronize()
+        check(name)
+        ms, ev = time_calls(fn, args.steps, args.warmup)
+        check(name)
+        out[name] = {"ms": ms, "p50_ms": float(np.percentile(ev, 50)),
+                     "p99_ms": float(np.percentile(ev, 99)), "attestations_per_s": w.n / (ms / 1e3),
+                     "pct_peak_int32_valu": 100.0 * comp * I_REF / (ms / 1e3) / 1e12 / PEAK_INT32_TOPS}
+        log("%-17s %.3f ms  (p99 %.3f)  %.3g tx/s" % (name, ms, out[name]["p99_ms"],
+                                                      out[name]["attestations_per_s"]))
+    g.close()
+    return {
+        "metric": METRIC,
+        "value": out["graph"]["attestations_per_s"],
+        "unit": "attestations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["graph"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batching, 256 blocks lognormal(19,500, 1.0) in [1k, 200k]",
+                   "n_tx": w.n, "n_id": w.n_id, "ids": "zipf 1.1", "keys": "resident midstates",
+                   "block_sizes_min_max": [int(w.block_sizes.min()), int(w.block_sizes.max())]},
+        "forms": out,
+        "speedup_graph_vs_per_block": out["per_block_calls"]["ms"] / out["graph"]["ms"],
+        "p99_ms": out["graph"]["p99_ms"],
+        "device": torch.cuda.get_device_name(0),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +165,11 @@ def main() -> int:
     ap.add_argument("--keys", choices=["recomputed", "midstate"], default="recomputed",
                     help="derive every identity's key in the step, or use resident midstates")
     ap.add_argument("--mode", choices=["binned", "binned-persistent", "ordered"], default="binned")
+    ap.add_argument("--workload", choices=["sweep", "batching"], default="sweep",
+                    help="sweep: the throughput sweep (default); batching: 256 uneven blocks")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run three plain device copies of this many bytes (a reference "
+                         "for scaling hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -89,6 +179,10 @@ def main() -> int:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(asked for --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         return 2
+
+    if args.workload == "batching":
+        print(json.dumps(bench_batching(args)), flush=True)
+        return 0
 
     from paper_2603_10242_amd import workload as W
     log("generating workload: %d txs, %d identities (%s ids)" % (args.n, args.n_id, args.ids))
@@ -104,6 +198,14 @@ def main() -> int:
     ace.load()
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("reference copies: 3 x %d bytes read and written" % args.copy_bytes)
+        del src, dst
     blk = ace.upload_block(w.msg, w.off, w.ids, w.tags)
     rev = ace.to_device(w.rev)
     if args.keys == "recomputed":

@@ -139,6 +139,55 @@ ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, ui
                              void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
 /*
+ * Tuning of the launch shapes (process-wide).  The autotuner measures the
+ * candidates on the device and installs the fastest with ace_set_tuning.
+ *   binned_min_tx      batches of at least this many transactions are binned
+ *                      by block count when the caller leaves the mode open
+ *   verify_wgs_per_cu  workgroups per CU of the persistent verify kernel and
+ *                      of the graph's in-order verify ("tiles per CU")
+ *   aux_wgs_per_cu     workgroups per CU of the binning and finalize passes
+ *   auto_persistent    1: binned batches in the open mode use the persistent
+ *                      verify kernel
+ * ace_set_tuning rejects workgroup counts outside 1..64.
+ */
+typedef struct {
+    uint64_t binned_min_tx;
+    uint32_t verify_wgs_per_cu;
+    uint32_t aux_wgs_per_cu;
+    uint32_t auto_persistent;
+} ace_tuning;
+
+ACE_API int ace_get_tuning(ace_tuning *out);
+ACE_API int ace_set_tuning(const ace_tuning *t);
+
+/*
+ * Captured batches (hipGraph).  ace_graph_create captures the whole pass for
+ * up to max_blocks blocks and max_tx transactions in all, with the keyset
+ * fixed, into two graph instances that read their block list from pinned host
+ * memory through a device-side plan kernel; so one capture replays for any
+ * mix of block count, block sizes and message lengths within the maxima.
+ * Every grid is fixed: the verify kernel is the persistent one (binned mode)
+ * or a grid-stride in-order one (flag ACE_ORDERED).
+ *   d_workspace  at least ace_graph_workspace_size() bytes, 256-byte aligned,
+ *                owned by the graph until ace_graph_destroy.
+ * ace_graph_launch enqueues one replay on `stream` for the given blocks (the
+ * same validity rules as ace_verify_batch).  Replays must be ordered on one
+ * stream (they share the workspace).  The call blocks only when the pinned
+ * block list it is about to reuse still belongs to the replay before the
+ * previous one.  The keyset's device arrays must outlive the graph.
+ * ace_graph_destroy waits for outstanding replays and frees the graph.
+ */
+typedef struct ace_graph ace_graph;
+
+ACE_API size_t ace_graph_workspace_size(const ace_keyset *keys, uint32_t max_blocks,
+                                        uint64_t max_tx, uint32_t flags);
+ACE_API int ace_graph_create(const ace_keyset *keys, uint32_t max_blocks, uint64_t max_tx,
+                             void *d_workspace, size_t ws_bytes, uint32_t flags, ace_graph **out);
+ACE_API int ace_graph_launch(ace_graph *g, const ace_block *blocks, uint32_t n_blocks,
+                             void *stream);
+ACE_API int ace_graph_destroy(ace_graph *g);
+
+/*
  * Stage timing (tracing).  While enabled on the calling thread, every
  * ace_verify_batch call records HIP events on its own stream around its
  * stages: key derivation, length binning (count, scan, scatter), the verify

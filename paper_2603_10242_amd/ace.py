@@ -55,6 +55,11 @@ class ace_keyset(ctypes.Structure):
                 ("info_len", ctypes.c_size_t)]
 
 
+class ace_tuning(ctypes.Structure):
+    _fields_ = [("binned_min_tx", ctypes.c_uint64), ("verify_wgs_per_cu", ctypes.c_uint32),
+                ("aux_wgs_per_cu", ctypes.c_uint32), ("auto_persistent", ctypes.c_uint32)]
+
+
 class ace_profile(ctypes.Structure):
     _fields_ = [("derive_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
                 ("verify_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
@@ -83,6 +88,14 @@ def load(path: str = LIB_PATH):
     lib.ace_verify_batch.argtypes = [ctypes.POINTER(ace_keyset), ctypes.POINTER(ace_block), u32,
                                      vp, sz, u32, vp]
     lib.ace_verify_batch.restype = ctypes.c_int
+    lib.ace_get_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
+    lib.ace_set_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
+    lib.ace_graph_workspace_size.argtypes = [ctypes.POINTER(ace_keyset), u32, ctypes.c_uint64, u32]
+    lib.ace_graph_workspace_size.restype = sz
+    lib.ace_graph_create.argtypes = [ctypes.POINTER(ace_keyset), u32, ctypes.c_uint64, vp, sz, u32,
+                                     ctypes.POINTER(vp)]
+    lib.ace_graph_launch.argtypes = [vp, ctypes.POINTER(ace_block), u32, vp]
+    lib.ace_graph_destroy.argtypes = [vp]
     lib.ace_profile_enable.argtypes = [ctypes.c_int]
     lib.ace_profile_enable.restype = ctypes.c_int
     lib.ace_profile_read.argtypes = [ctypes.POINTER(ace_profile), ctypes.c_int]
@@ -246,3 +259,52 @@ def profile_read(reset: bool = True) -> dict:
     p = ace_profile()
     _check(load().ace_profile_read(ctypes.byref(p), 1 if reset else 0))
     return {k: getattr(p, k) for k, _ in ace_profile._fields_}
+
+
+def get_tuning() -> dict:
+    t = ace_tuning()
+    _check(load().ace_get_tuning(ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in ace_tuning._fields_}
+
+
+def set_tuning(**kw) -> dict:
+    """ace_set_tuning: updates the given fields, returns the previous tuning."""
+    old = get_tuning()
+    new = dict(old)
+    new.update(kw)
+    t = ace_tuning(*[int(new[k]) for k, _ in ace_tuning._fields_])
+    _check(load().ace_set_tuning(ctypes.byref(t)))
+    return old
+
+
+class Graph:
+    """ace_graph_*: one capture of the whole pass, replayed for any block mix."""
+
+    def __init__(self, keyset: DeviceKeyset, max_blocks: int, max_tx: int, flags: int = 0,
+                 device="cuda"):
+        lib = load()
+        self._ks, self._keep = keyset.struct()
+        self.keyset = keyset
+        need = int(lib.ace_graph_workspace_size(ctypes.byref(self._ks), max_blocks, max_tx, flags))
+        if need == 0:
+            raise AceError(ACE_ERR_INVALID_ARG, "bad graph arguments")
+        self.ws = workspace(need, device=device)
+        h = ctypes.c_void_p()
+        _check(lib.ace_graph_create(ctypes.byref(self._ks), max_blocks, max_tx, _ptr(self.ws),
+                                    self.ws.numel(), flags, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, blocks: Sequence[DeviceBlock], stream=None) -> None:
+        arr = _blocks_array(blocks)
+        _check(load().ace_graph_launch(self._h, arr, len(blocks), _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().ace_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

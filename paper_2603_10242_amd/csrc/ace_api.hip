@@ -1,8 +1,8 @@
 // ace_api.hip -- host entry points of libace.so (declared in include/ace.h).
 //
-// Argument checking, workspace layout and the launch sequence.  Nothing here
-// computes any part of the attestation check: every hash runs in the kernels
-// of ace_kernels.hip.
+// Argument checking, workspace layout, launch sequences, graph capture and
+// stage timing.  Nothing here computes any part of the attestation check:
+// every hash runs in the kernels of ace_kernels.hip.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -63,24 +63,26 @@ int cu_count()
     return cache[dev];
 }
 
-int fill_hkdf(HkdfParams &hp, const uint8_t *salt, size_t salt_len, const uint8_t *info,
-              size_t info_len)
+// ------------------------------------------------------------------------------------------
+// Tuning (set by the autotuner through ace_set_tuning).
+// ------------------------------------------------------------------------------------------
+std::mutex g_tune_mu;
+ace_tuning g_tune = {
+    /* binned_min_tx     */ 1u << 18,
+    /* verify_wgs_per_cu */ 8,
+    /* aux_wgs_per_cu    */ 8,
+    /* auto_persistent   */ 0,
+};
+
+ace_tuning tuning()
 {
-    if (salt_len > kMaxSalt)
-        return fail(ACE_ERR_INVALID_ARG, "salt_len %zu exceeds %u", salt_len, kMaxSalt);
-    if (info_len > kMaxInfo)
-        return fail(ACE_ERR_INVALID_ARG, "info_len %zu exceeds %u", info_len, kMaxInfo);
-    if (salt_len && !salt) return fail(ACE_ERR_INVALID_ARG, "h_salt is NULL with salt_len > 0");
-    if (info_len && !info) return fail(ACE_ERR_INVALID_ARG, "h_info is NULL with info_len > 0");
-    memset(&hp, 0, sizeof hp);
-    hp.salt_len = (uint32_t)salt_len;
-    hp.info_len = (uint32_t)info_len;
-    if (salt_len) memcpy(hp.salt, salt, salt_len);
-    if (info_len) memcpy(hp.info, info, info_len);
-    return ACE_OK;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune;
 }
 
+// ------------------------------------------------------------------------------------------
 // Stage timing: one set of events per profiled call, reused after a reset.
+// ------------------------------------------------------------------------------------------
 struct ProfCall {
     hipEvent_t ev[5];  // start, after derive, after binning, after verify, end
 };
@@ -115,31 +117,45 @@ inline void prof_mark(ProfCall *c, int k, hipStream_t s)
     if (c) hipEventRecord(c->ev[k], s);
 }
 
-enum Mode { kOrdered, kBinned };
+// ------------------------------------------------------------------------------------------
+// Arguments, plan and workspace layout.
+// ------------------------------------------------------------------------------------------
+int fill_hkdf(HkdfParams &hp, const uint8_t *salt, size_t salt_len, const uint8_t *info,
+              size_t info_len)
+{
+    if (salt_len > kMaxSalt)
+        return fail(ACE_ERR_INVALID_ARG, "salt_len %zu exceeds %u", salt_len, kMaxSalt);
+    if (info_len > kMaxInfo)
+        return fail(ACE_ERR_INVALID_ARG, "info_len %zu exceeds %u", info_len, kMaxInfo);
+    if (salt_len && !salt) return fail(ACE_ERR_INVALID_ARG, "h_salt is NULL with salt_len > 0");
+    if (info_len && !info) return fail(ACE_ERR_INVALID_ARG, "h_info is NULL with info_len > 0");
+    memset(&hp, 0, sizeof hp);
+    hp.salt_len = (uint32_t)salt_len;
+    hp.info_len = (uint32_t)info_len;
+    if (salt_len) memcpy(hp.salt, salt, salt_len);
+    if (info_len) memcpy(hp.info, info, info_len);
+    return ACE_OK;
+}
 
-// Batches at or above this many transactions are binned by length unless
-// the caller says otherwise.
-constexpr uint64_t kAutoBinnedMin = 1u << 18;
+enum Mode { kOrdered, kBinned };
 
 struct Plan {
     Mode mode;
     bool per_tx;
     bool persistent;
     bool rev;
+    uint32_t n_blocks;
     uint64_t total_tx;
     uint64_t total_tiles;
     uint64_t total_waves;
-    uint64_t max_pos;     // upper bound of bin-order positions
+    uint64_t max_pos;  // upper bound of bin-order positions
     // workspace layout (byte offsets)
-    size_t off_ctrl, off_descs, off_mid, off_perm, off_posof, off_vperm, bytes;
+    size_t off_ctrl, off_hdr, off_descs, off_mid, off_perm, off_posof, off_vperm, bytes;
 };
 
-int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks, uint32_t flags,
-              Plan &p)
+int check_keyset(const ace_keyset *keys, uint32_t flags, Plan &p)
 {
     if (!keys) return fail(ACE_ERR_INVALID_ARG, "keys is NULL");
-    if (n_blocks && !blocks) return fail(ACE_ERR_INVALID_ARG, "blocks is NULL");
-    if (n_blocks >= (1u << 24)) return fail(ACE_ERR_RANGE, "n_blocks %u >= 2^24", n_blocks);
     const uint32_t known = ACE_ORDERED | ACE_BUCKETED | ACE_PERSISTENT | ACE_PER_TX_KEYS;
     if (flags & ~known) return fail(ACE_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & ACE_ORDERED) && (flags & ACE_BUCKETED))
@@ -148,7 +164,8 @@ int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks
         return fail(ACE_ERR_INVALID_ARG, "unknown keyset kind %d", keys->kind);
     p.rev = keys->kind == ACE_KEYS_REV;
     p.per_tx = (flags & ACE_PER_TX_KEYS) != 0;
-    if (p.per_tx && !p.rev) return fail(ACE_ERR_INVALID_ARG, "ACE_PER_TX_KEYS needs a keyset of kind ACE_KEYS_REV");
+    if (p.per_tx && !p.rev)
+        return fail(ACE_ERR_INVALID_ARG, "ACE_PER_TX_KEYS needs a keyset of kind ACE_KEYS_REV");
     if (keys->n_id) {
         if (p.rev) {
             if (!keys->d_rev) return fail(ACE_ERR_INVALID_ARG, "keyset d_rev is NULL");
@@ -164,11 +181,20 @@ int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks
         if ((keys->salt_len && !keys->h_salt) || (keys->info_len && !keys->h_info))
             return fail(ACE_ERR_INVALID_ARG, "keyset h_salt/h_info is NULL");
     }
-    uint64_t total = 0, tiles = 0, waves = 0;
+    return ACE_OK;
+}
+
+int check_blocks(const ace_block *blocks, uint32_t n_blocks, uint64_t &total, uint64_t &tiles,
+                 uint64_t &waves)
+{
+    if (n_blocks && !blocks) return fail(ACE_ERR_INVALID_ARG, "blocks is NULL");
+    if (n_blocks >= (1u << 24)) return fail(ACE_ERR_RANGE, "n_blocks %u >= 2^24", n_blocks);
+    total = tiles = waves = 0;
     for (uint32_t b = 0; b < n_blocks; ++b) {
         const ace_block &k = blocks[b];
         if (!k.d_count_out) return fail(ACE_ERR_INVALID_ARG, "block %u: d_count_out is NULL", b);
-        if (!aligned(k.d_count_out, 8)) return fail(ACE_ERR_INVALID_ARG, "block %u: d_count_out not 8-byte aligned", b);
+        if (!aligned(k.d_count_out, 8))
+            return fail(ACE_ERR_INVALID_ARG, "block %u: d_count_out not 8-byte aligned", b);
         if (k.n_tx) {
             if (!k.d_off || !k.d_id || !k.d_tag || !k.d_bitmask_out || !k.d_msg)
                 return fail(ACE_ERR_INVALID_ARG, "block %u: NULL array with n_tx > 0", b);
@@ -182,24 +208,46 @@ int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks
         tiles += (k.n_tx + kTile - 1) / kTile;
         waves += (k.n_tx + 63) / 64;
     }
-    p.total_tx = total;
-    p.total_tiles = tiles;
-    p.total_waves = waves;
+    return ACE_OK;
+}
+
+// Mode, persistence and workspace layout for n_blocks blocks of `total`
+// transactions in all (exact sizes for a call, maxima for a graph).
+void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t flags, bool graph,
+            Plan &p)
+{
+    const ace_tuning t = tuning();
+    p.n_blocks = n_blocks;
     if (flags & ACE_ORDERED) p.mode = kOrdered;
     else if (flags & ACE_BUCKETED) p.mode = kBinned;
-    else p.mode = total >= kAutoBinnedMin ? kBinned : kOrdered;
-    p.persistent = (flags & ACE_PERSISTENT) != 0 && p.mode == kBinned;
+    else p.mode = total >= t.binned_min_tx ? kBinned : kOrdered;
+    const bool binned = p.mode == kBinned;
+    p.persistent = binned && (graph || (flags & ACE_PERSISTENT) ||
+                              (!(flags & (ACE_ORDERED | ACE_BUCKETED)) && t.auto_persistent));
     p.max_pos = total + 64ull * kBins;
-
+    const bool table = graph || n_blocks > 1;
     size_t o = 0;
     p.off_ctrl = o;  o = align_up(o + sizeof(Ctrl), 256);
-    p.off_descs = o; o = align_up(o + (n_blocks > 1 ? n_blocks * sizeof(DevBlock) : 0), 256);
+    p.off_hdr = o;   o = align_up(o + (graph ? sizeof(BatchHdr) : 0), 256);
+    p.off_descs = o; o = align_up(o + (table ? (size_t)n_blocks * sizeof(DevBlock) : 0), 256);
     p.off_mid = o;   o = align_up(o + (p.rev && !p.per_tx ? 64ull * keys->n_id : 0), 256);
-    const bool binned = p.mode == kBinned;
     p.off_perm = o;  o = align_up(o + (binned ? 8ull * p.max_pos : 0), 256);
     p.off_posof = o; o = align_up(o + (binned ? 4ull * total : 0), 256);
     p.off_vperm = o; o = align_up(o + (binned ? 4ull * (p.max_pos / 32 + 2) : 0), 256);
     p.bytes = o;
+}
+
+int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks, uint32_t flags,
+              Plan &p)
+{
+    int rc = check_keyset(keys, flags, p);
+    if (rc) return rc;
+    uint64_t total, tiles, waves;
+    if ((rc = check_blocks(blocks, n_blocks, total, tiles, waves))) return rc;
+    p.total_tx = total;
+    p.total_tiles = tiles;
+    p.total_waves = waves;
+    layout(keys, n_blocks, total, flags, false, p);
     return ACE_OK;
 }
 
@@ -211,13 +259,176 @@ unsigned grid_for(uint64_t items, uint64_t per_wg, unsigned cap)
     return (unsigned)g;
 }
 
+DevBlock dev_block(const ace_block &k)
+{
+    DevBlock d;
+    memset(&d, 0, sizeof d);
+    d.msg = k.d_msg;
+    d.off = k.d_off;
+    d.id = k.d_id;
+    d.tag = k.d_tag;
+    d.bitmask = k.d_bitmask_out;
+    d.count = reinterpret_cast<unsigned long long *>(k.d_count_out);
+    d.n = k.n_tx;
+    return d;
+}
+
+// The launch sequence after the block table is in place.  `graph` marks a
+// capture: sizes then come from the device header and every grid is fixed.
+int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const HkdfParams &hp,
+                   uint8_t *ws, hipStream_t s, ProfCall *prof, bool graph)
+{
+    int rc;
+    const ace_tuning tn = tuning();
+    const unsigned cus = (unsigned)cu_count();
+    Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+    const bool binned = p.mode == kBinned;
+
+    KeySource ks;
+    ks.n_id = keys->n_id;
+    ks.mid = nullptr;
+    ks.rev = nullptr;
+    if (!p.rev) {
+        ks.mid = keys->d_mid;
+    } else if (p.per_tx) {
+        ks.rev = keys->d_rev;
+    } else {
+        uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
+        if (keys->n_id) {
+            const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
+            hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, s, keys->d_rev, keys->n_id,
+                               (uint8_t *)nullptr, mid, hp);
+            if ((rc = launch_status("k_derive launch"))) return rc;
+        }
+        ks.mid = mid;
+    }
+    prof_mark(prof, 1, s);
+
+    if (!graph) {
+        hipLaunchKernelGGL(k_zero, dim3(grid_for(p.n_blocks, kWG, 1024)), dim3(kWG), 0, s, bt,
+                           binned ? ctrl : (Ctrl *)nullptr);
+        if ((rc = launch_status("k_zero launch"))) return rc;
+    }
+
+    if (!binned) {
+        prof_mark(prof, 2, s);
+        if (graph || p.total_tx) {
+            const unsigned g = graph ? tn.verify_wgs_per_cu * cus
+                                     : grid_for(p.total_waves, kWavesPerWG, 0x7fffffffu);
+            if (p.per_tx)
+                hipLaunchKernelGGL(k_verify_ordered<true>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+            else
+                hipLaunchKernelGGL(k_verify_ordered<false>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+            if ((rc = launch_status("k_verify_ordered launch"))) return rc;
+        }
+        prof_mark(prof, 3, s);
+        prof_mark(prof, 4, s);
+        return ACE_OK;
+    }
+    if (!graph && p.total_tx == 0) {
+        for (int k = 2; k <= 4; ++k) prof_mark(prof, k, s);
+        return ACE_OK;
+    }
+
+    unsigned long long *perm = reinterpret_cast<unsigned long long *>(ws + p.off_perm);
+    uint32_t *pos_of = reinterpret_cast<uint32_t *>(ws + p.off_posof);
+    uint32_t *vperm = reinterpret_cast<uint32_t *>(ws + p.off_vperm);
+    const uint64_t tiles_bound = graph ? (p.total_tx + kTile - 1) / kTile + p.n_blocks : p.total_tiles;
+    const unsigned gtiles = grid_for(tiles_bound, 1, tn.aux_wgs_per_cu * cus);
+
+    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl);
+    if ((rc = launch_status("k_bin_count launch"))) return rc;
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
+    if ((rc = launch_status("k_bin_scan launch"))) return rc;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, perm, pos_of);
+    if ((rc = launch_status("k_bin_scatter launch"))) return rc;
+    prof_mark(prof, 2, s);
+
+    if (p.persistent) {
+        const unsigned g = tn.verify_wgs_per_cu * cus;
+        if (p.per_tx)
+            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+        else
+            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+    } else {
+        const unsigned g = grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
+        if (p.per_tx)
+            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+        else
+            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+    }
+    if ((rc = launch_status("k_verify_binned launch"))) return rc;
+    prof_mark(prof, 3, s);
+    hipLaunchKernelGGL(k_finalize, dim3(gtiles), dim3(kWG), 0, s, bt, pos_of, vperm);
+    if ((rc = launch_status("k_finalize launch"))) return rc;
+    prof_mark(prof, 4, s);
+    return ACE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Graph object.
+// ------------------------------------------------------------------------------------------
+struct ace_graph {
+    int device;
+    Plan plan;
+    uint32_t max_blocks;
+    uint64_t max_tx;
+    struct Slot {
+        DevBlock *h_descs;  // pinned, read by k_plan at replay time
+        uint32_t *h_n;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        hipEvent_t done;
+        bool used;
+    } slot[2];
+    int next;
+    hipStream_t capture;
+};
+
+namespace {
+
+void graph_free(ace_graph *g)
+{
+    if (!g) return;
+    for (auto &sl : g->slot) {
+        if (sl.exec) hipGraphExecDestroy(sl.exec);
+        if (sl.graph) hipGraphDestroy(sl.graph);
+        if (sl.done) hipEventDestroy(sl.done);
+        if (sl.h_descs) hipHostFree(sl.h_descs);
+    }
+    if (g->capture) hipStreamDestroy(g->capture);
+    delete g;
+}
+
 }  // namespace
 
 extern "C" {
 
 ACE_API const char *ace_last_error(void) { return g_err; }
 
-ACE_API const char *ace_version(void) { return "ace 0.1 gfx950"; }
+ACE_API const char *ace_version(void) { return "ace 0.2 gfx950"; }
+
+ACE_API int ace_get_tuning(ace_tuning *out)
+{
+    clear_error();
+    if (!out) return fail(ACE_ERR_INVALID_ARG, "out is NULL");
+    *out = tuning();
+    return ACE_OK;
+}
+
+ACE_API int ace_set_tuning(const ace_tuning *t)
+{
+    clear_error();
+    if (!t) return fail(ACE_ERR_INVALID_ARG, "tuning is NULL");
+    if (t->verify_wgs_per_cu < 1 || t->verify_wgs_per_cu > 64 || t->aux_wgs_per_cu < 1 ||
+        t->aux_wgs_per_cu > 64)
+        return fail(ACE_ERR_INVALID_ARG, "workgroups per CU must be in 1..64");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = *t;
+    return ACE_OK;
+}
 
 ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *h_salt,
                             size_t salt_len, const uint8_t *h_info, size_t info_len,
@@ -260,131 +471,45 @@ ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, ui
         return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
     HkdfParams hp;
     memset(&hp, 0, sizeof hp);
-    if (p.rev) {
-        rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len);
-        if (rc) return rc;
-    }
+    if (p.rev && (rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len)))
+        return rc;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     ProfCall *prof = prof_begin(s);
     uint8_t *ws = static_cast<uint8_t *>(d_workspace);
-    Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
     DevBlock *table = reinterpret_cast<DevBlock *>(ws + p.off_descs);
 
-    // block descriptors with their prefixes
     Batch bt;
     memset(&bt, 0, sizeof bt);
     bt.n_blocks = n_blocks;
     bt.total_tx = p.total_tx;
     bt.total_tiles = p.total_tiles;
     bt.total_waves = p.total_waves;
-    {
-        DescChunk chunk;
-        memset(&chunk, 0, sizeof chunk);
-        uint64_t tx0 = 0, tile0 = 0, wave0 = 0;
-        for (uint32_t b = 0; b < n_blocks; ++b) {
-            const ace_block &k = blocks[b];
-            DevBlock d;
-            d.msg = k.d_msg;
-            d.off = k.d_off;
-            d.id = k.d_id;
-            d.tag = k.d_tag;
-            d.bitmask = k.d_bitmask_out;
-            d.count = reinterpret_cast<unsigned long long *>(k.d_count_out);
-            d.n = k.n_tx;
-            d.tx0 = tx0;
-            d.tile0 = tile0;
-            d.wave0 = wave0;
-            tx0 += k.n_tx;
-            tile0 += (k.n_tx + kTile - 1) / kTile;
-            wave0 += (k.n_tx + 63) / 64;
-            if (n_blocks == 1) {
-                bt.one = d;
-                break;
-            }
-            chunk.d[chunk.count++] = d;
-            if (chunk.count == kDescChunk || b + 1 == n_blocks) {
-                hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, table, chunk);
-                if ((rc = launch_status("k_put_descs launch"))) return rc;
-                chunk.first = b + 1;
-                chunk.count = 0;
-            }
+    DescChunk chunk;
+    memset(&chunk, 0, sizeof chunk);
+    uint64_t tx0 = 0, tile0 = 0, wave0 = 0;
+    for (uint32_t b = 0; b < n_blocks; ++b) {
+        DevBlock d = dev_block(blocks[b]);
+        d.tx0 = tx0;
+        d.tile0 = tile0;
+        d.wave0 = wave0;
+        tx0 += d.n;
+        tile0 += (d.n + kTile - 1) / kTile;
+        wave0 += (d.n + 63) / 64;
+        if (n_blocks == 1) {
+            bt.one = d;
+            break;
         }
-        bt.table = n_blocks > 1 ? table : nullptr;
-    }
-
-    KeySource ks;
-    ks.n_id = keys->n_id;
-    ks.mid = nullptr;
-    ks.rev = nullptr;
-    if (!p.rev) {
-        ks.mid = keys->d_mid;
-    } else if (p.per_tx) {
-        ks.rev = keys->d_rev;
-    } else {
-        uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
-        if (keys->n_id) {
-            const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
-            hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, s, keys->d_rev, keys->n_id,
-                               (uint8_t *)nullptr, mid, hp);
-            if ((rc = launch_status("k_derive launch"))) return rc;
+        chunk.d[chunk.count++] = d;
+        if (chunk.count == kDescChunk || b + 1 == n_blocks) {
+            hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, table, chunk);
+            if ((rc = launch_status("k_put_descs launch"))) return rc;
+            chunk.first = b + 1;
+            chunk.count = 0;
         }
-        ks.mid = mid;
     }
-    prof_mark(prof, 1, s);
-
-    const bool binned = p.mode == kBinned;
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(n_blocks, kWG, 1024)), dim3(kWG), 0, s, bt,
-                       binned ? ctrl : (Ctrl *)nullptr);
-    if ((rc = launch_status("k_zero launch"))) return rc;
-    if (p.total_tx == 0 || !binned) {
-        prof_mark(prof, 2, s);
-        if (p.total_tx) {
-            const unsigned g = grid_for(p.total_waves, kWavesPerWG, 0x7fffffffu);
-            if (p.per_tx)
-                hipLaunchKernelGGL(k_verify_ordered<true>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
-            else
-                hipLaunchKernelGGL(k_verify_ordered<false>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
-            if ((rc = launch_status("k_verify_ordered launch"))) return rc;
-        }
-        prof_mark(prof, 3, s);
-        prof_mark(prof, 4, s);
-        return ACE_OK;
-    }
-
-    unsigned long long *perm = reinterpret_cast<unsigned long long *>(ws + p.off_perm);
-    uint32_t *pos_of = reinterpret_cast<uint32_t *>(ws + p.off_posof);
-    uint32_t *vperm = reinterpret_cast<uint32_t *>(ws + p.off_vperm);
-    const unsigned cus = (unsigned)cu_count();
-    const unsigned gtiles = grid_for(p.total_tiles, 1, 8 * cus);
-
-    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl);
-    if ((rc = launch_status("k_bin_count launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
-    if ((rc = launch_status("k_bin_scan launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, perm, pos_of);
-    if ((rc = launch_status("k_bin_scatter launch"))) return rc;
-    prof_mark(prof, 2, s);
-
-    if (p.persistent) {
-        const unsigned g = 8 * cus;
-        if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
-        else
-            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
-    } else {
-        const unsigned g = grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
-        if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
-        else
-            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
-    }
-    if ((rc = launch_status("k_verify_binned launch"))) return rc;
-    prof_mark(prof, 3, s);
-    hipLaunchKernelGGL(k_finalize, dim3(gtiles), dim3(kWG), 0, s, bt, pos_of, vperm);
-    if ((rc = launch_status("k_finalize launch"))) return rc;
-    prof_mark(prof, 4, s);
-    return ACE_OK;
+    bt.table = n_blocks > 1 ? table : nullptr;
+    return enqueue_stages(p, bt, keys, hp, ws, s, prof, false);
 }
 
 ACE_API int ace_profile_enable(int on)
@@ -416,6 +541,137 @@ ACE_API int ace_profile_read(ace_profile *out, int reset)
         out->calls += 1;
     }
     if (reset) g_prof.used = 0;
+    return ACE_OK;
+}
+
+ACE_API size_t ace_graph_workspace_size(const ace_keyset *keys, uint32_t max_blocks, uint64_t max_tx,
+                                        uint32_t flags)
+{
+    Plan p;
+    if (check_keyset(keys, flags, p) != ACE_OK) return 0;
+    if (max_blocks == 0 || max_blocks >= (1u << 24) || max_tx > ACE_MAX_TX) return 0;
+    layout(keys, max_blocks, max_tx, flags, true, p);
+    return p.bytes;
+}
+
+ACE_API int ace_graph_create(const ace_keyset *keys, uint32_t max_blocks, uint64_t max_tx,
+                             void *d_workspace, size_t ws_bytes, uint32_t flags, ace_graph **out)
+{
+    clear_error();
+    if (!out) return fail(ACE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    int rc = check_keyset(keys, flags, p);
+    if (rc) return rc;
+    if (max_blocks == 0) return fail(ACE_ERR_INVALID_ARG, "max_blocks is 0");
+    if (max_blocks >= (1u << 24)) return fail(ACE_ERR_RANGE, "max_blocks >= 2^24");
+    if (max_tx > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "max_tx exceeds ACE_MAX_TX");
+    layout(keys, max_blocks, max_tx, flags, true, p);
+    p.total_tx = max_tx;
+    p.total_tiles = 0;
+    p.total_waves = 0;
+    if (!d_workspace || !aligned(d_workspace, 256))
+        return fail(ACE_ERR_INVALID_ARG, "d_workspace NULL or not 256-byte aligned");
+    if (ws_bytes < p.bytes) return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
+    HkdfParams hp;
+    memset(&hp, 0, sizeof hp);
+    if (p.rev && (rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len)))
+        return rc;
+
+    (void)cu_count();  // device queries happen before the capture starts
+    ace_graph *g = new ace_graph;
+    memset(g, 0, sizeof *g);
+    g->plan = p;
+    g->max_blocks = max_blocks;
+    g->max_tx = max_tx;
+    if ((rc = check_hip(hipGetDevice(&g->device), "hipGetDevice")) ||
+        (rc = check_hip(hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking), "hipStreamCreate"))) {
+        graph_free(g);
+        return rc;
+    }
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    Ctrl *ctrl = reinterpret_cast<Ctrl *>(ws + p.off_ctrl);
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(ws + p.off_hdr);
+    DevBlock *table = reinterpret_cast<DevBlock *>(ws + p.off_descs);
+    for (auto &sl : g->slot) {
+        void *h = nullptr;
+        const size_t hb = align_up((size_t)max_blocks * sizeof(DevBlock), 256) + 256;
+        if ((rc = check_hip(hipHostMalloc(&h, hb, hipHostMallocDefault), "hipHostMalloc")) ||
+            (rc = check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate"))) {
+            if (h && !sl.h_descs) hipHostFree(h);
+            graph_free(g);
+            return rc;
+        }
+        memset(h, 0, hb);
+        sl.h_descs = static_cast<DevBlock *>(h);
+        sl.h_n = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(h) + hb - 256);
+        void *dh = nullptr;  // the same pinned buffer as the device addresses it
+        if ((rc = check_hip(hipHostGetDevicePointer(&dh, h, 0), "hipHostGetDevicePointer"))) {
+            graph_free(g);
+            return rc;
+        }
+        const DevBlock *d_descs = static_cast<const DevBlock *>(dh);
+        const uint32_t *d_n = reinterpret_cast<const uint32_t *>(static_cast<uint8_t *>(dh) + hb - 256);
+
+        Batch bt;
+        memset(&bt, 0, sizeof bt);
+        bt.table = table;
+        bt.hdr = hdr;
+        bt.n_blocks = max_blocks;
+        if ((rc = check_hip(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal),
+                            "hipStreamBeginCapture"))) {
+            graph_free(g);
+            return rc;
+        }
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanWG), 0, g->capture, d_descs, d_n,
+                           max_blocks, table, hdr, p.mode == kBinned ? ctrl : (Ctrl *)nullptr);
+        rc = launch_status("k_plan launch");
+        if (!rc) rc = enqueue_stages(p, bt, keys, hp, ws, g->capture, nullptr, true);
+        hipGraph_t graph = nullptr;
+        const int rc_end = check_hip(hipStreamEndCapture(g->capture, &graph), "hipStreamEndCapture");
+        sl.graph = graph;
+        if (rc || (rc = rc_end) ||
+            (rc = check_hip(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0),
+                            "hipGraphInstantiate"))) {
+            graph_free(g);
+            return rc;
+        }
+    }
+    *out = g;
+    return ACE_OK;
+}
+
+ACE_API int ace_graph_launch(ace_graph *g, const ace_block *blocks, uint32_t n_blocks, void *stream)
+{
+    clear_error();
+    if (!g) return fail(ACE_ERR_INVALID_ARG, "graph is NULL");
+    if (n_blocks > g->max_blocks)
+        return fail(ACE_ERR_RANGE, "n_blocks %u exceeds the graph's %u", n_blocks, g->max_blocks);
+    uint64_t total, tiles, waves;
+    int rc = check_blocks(blocks, n_blocks, total, tiles, waves);
+    if (rc) return rc;
+    if (total > g->max_tx)
+        return fail(ACE_ERR_RANGE, "%llu transactions exceed the graph's %llu",
+                    (unsigned long long)total, (unsigned long long)g->max_tx);
+    auto &sl = g->slot[g->next];
+    if (sl.used && (rc = check_hip(hipEventSynchronize(sl.done), "hipEventSynchronize"))) return rc;
+    for (uint32_t b = 0; b < n_blocks; ++b) sl.h_descs[b] = dev_block(blocks[b]);
+    *sl.h_n = n_blocks;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_hip(hipGraphLaunch(sl.exec, s), "hipGraphLaunch"))) return rc;
+    if ((rc = check_hip(hipEventRecord(sl.done, s), "hipEventRecord"))) return rc;
+    sl.used = true;
+    g->next ^= 1;
+    return ACE_OK;
+}
+
+ACE_API int ace_graph_destroy(ace_graph *g)
+{
+    clear_error();
+    if (!g) return ACE_OK;
+    for (auto &sl : g->slot)
+        if (sl.used) hipEventSynchronize(sl.done);
+    graph_free(g);
     return ACE_OK;
 }
 

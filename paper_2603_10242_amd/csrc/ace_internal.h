@@ -29,11 +29,23 @@ struct DevBlock {
     uint64_t wave0;  // first wave tile of the in-order verify (64 per wave)
 };
 
+// Sizes of a call that a captured graph reads from device memory (they
+// change from replay to replay while the kernel arguments stay fixed).
+struct BatchHdr {
+    uint32_t n_blocks;
+    uint32_t pad_;
+    uint64_t total_tx;
+    uint64_t total_tiles;
+    uint64_t total_waves;
+};
+
 // Blocks of one call: a single block travels inline in the kernel arguments,
-// several blocks in a device table.
+// several blocks in a device table.  When `hdr` is set, the block count and
+// totals come from it and every block from the table.
 struct Batch {
     DevBlock one;
     const DevBlock *table;
+    const BatchHdr *hdr;
     uint32_t n_blocks;
     uint64_t total_tx;
     uint64_t total_tiles;

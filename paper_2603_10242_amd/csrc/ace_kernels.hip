@@ -37,19 +37,46 @@ __device__ __forceinline__ U4 load16(const uint32_t *p)
     return v;
 }
 
-__device__ __forceinline__ DevBlock get_block(const Batch &bt, uint32_t b)
+// Block count and totals of a call: kernel arguments, or the device header
+// of a graph replay.
+struct Totals {
+    uint32_t n_blocks;
+    bool inline_one;
+    uint64_t tx, tiles, waves;
+};
+
+__device__ __forceinline__ Totals totals(const Batch &bt)
 {
-    if (bt.n_blocks == 1) return bt.one;
+    Totals t;
+    if (bt.hdr) {
+        t.n_blocks = bt.hdr->n_blocks;
+        t.tx = bt.hdr->total_tx;
+        t.tiles = bt.hdr->total_tiles;
+        t.waves = bt.hdr->total_waves;
+        t.inline_one = false;
+    } else {
+        t.n_blocks = bt.n_blocks;
+        t.tx = bt.total_tx;
+        t.tiles = bt.total_tiles;
+        t.waves = bt.total_waves;
+        t.inline_one = bt.n_blocks == 1;
+    }
+    return t;
+}
+
+__device__ __forceinline__ DevBlock get_block(const Batch &bt, const Totals &T, uint32_t b)
+{
+    if (T.inline_one) return bt.one;
     return bt.table[b];
 }
 
 // Last block whose prefix (selected by `field`) is <= x; empty blocks share
 // their prefix with the next block, so the last match is the owner.
 template <int FIELD>
-__device__ __forceinline__ uint32_t find_block(const Batch &bt, uint64_t x)
+__device__ __forceinline__ uint32_t find_block(const Batch &bt, const Totals &T, uint64_t x)
 {
-    if (bt.n_blocks == 1) return 0;
-    uint32_t lo = 0, hi = bt.n_blocks;
+    if (T.n_blocks == 1) return 0;
+    uint32_t lo = 0, hi = T.n_blocks;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         const DevBlock &d = bt.table[mid];
@@ -408,23 +435,27 @@ __global__ void __launch_bounds__(kWG) k_verify_ordered(Batch bt, KeySource ks, 
         if (threadIdx.x < 64) hkdf_prepare(hp, prep);
         __syncthreads();
     }
-    const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
-    if (w >= bt.total_waves) return;
-    const uint32_t b = find_block<1>(bt, w);
-    const DevBlock d = get_block(bt, b);
-    const uint64_t i0 = 64ull * (w - d.wave0);
-    const uint64_t i = i0 + lane_id();
-    const bool active = i < d.n;
-    TxRef t{};
-    bool live = false;
-    if (active) live = load_tx(d, i, ks, t);
-    const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
-    const unsigned long long m = __ballot(valid);
-    if (lane_id() == 0) {
-        d.bitmask[i0 >> 5] = (uint32_t)m;
-        if (i0 + 32 < d.n) d.bitmask[(i0 >> 5) + 1] = (uint32_t)(m >> 32);
-        const unsigned c = __popcll(m);
-        if (c) atomicAdd(d.count, (unsigned long long)c);
+    const Totals T = totals(bt);
+    // grid-stride over wave tiles (wave-uniform loop bound)
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + wave; w < T.waves;
+         w += (uint64_t)gridDim.x * kWavesPerWG) {
+        const uint32_t b = find_block<1>(bt, T, w);
+        const DevBlock d = get_block(bt, T, b);
+        const uint64_t i0 = 64ull * (w - d.wave0);
+        const uint64_t i = i0 + lane_id();
+        const bool active = i < d.n;
+        TxRef t{};
+        bool live = false;
+        if (active) live = load_tx(d, i, ks, t);
+        const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
+        const unsigned long long m = __ballot(valid);
+        if (lane_id() == 0) {
+            d.bitmask[i0 >> 5] = (uint32_t)m;
+            if (i0 + 32 < d.n) d.bitmask[(i0 >> 5) + 1] = (uint32_t)(m >> 32);
+            const unsigned c = __popcll(m);
+            if (c) atomicAdd(d.count, (unsigned long long)c);
+        }
     }
 }
 
@@ -433,8 +464,9 @@ __global__ void __launch_bounds__(kWG) k_verify_ordered(Batch bt, KeySource ks, 
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
 {
+    const Totals T = totals(bt);
     const uint32_t t = blockIdx.x * kWG + threadIdx.x;
-    for (uint32_t b = t; b < bt.n_blocks; b += gridDim.x * kWG) *get_block(bt, b).count = 0;
+    for (uint32_t b = t; b < T.n_blocks; b += gridDim.x * kWG) *get_block(bt, T, b).count = 0;
     if (ctrl && blockIdx.x == 0 && threadIdx.x < kBins) {
         ctrl->hist[threadIdx.x] = 0;
         ctrl->cursor[threadIdx.x] = 0;
@@ -453,8 +485,9 @@ __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl)
     __shared__ uint32_t h[kBins];
     if (threadIdx.x < kBins) h[threadIdx.x] = 0;
     __syncthreads();
-    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
-        const DevBlock d = get_block(bt, find_block<0>(bt, tile));
+    const Totals T = totals(bt);
+    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+        const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
         for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
             const uint64_t i = i0 + k;
@@ -491,9 +524,10 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
     constexpr int kPer = kTile / kWG;
     __shared__ uint32_t cnt[kBins];
     __shared__ uint32_t base[kBins];
-    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
-        const uint32_t b = find_block<0>(bt, tile);
-        const DevBlock d = get_block(bt, b);
+    const Totals T = totals(bt);
+    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+        const uint32_t b = find_block<0>(bt, T, tile);
+        const DevBlock d = get_block(bt, T, b);
         const uint64_t i0 = (tile - d.tile0) * kTile;
         if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
         __syncthreads();
@@ -545,10 +579,12 @@ __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, H
         oend[threadIdx.x] = ctrl->ostart[threadIdx.x] + ctrl->opad[threadIdx.x];
     }
     __syncthreads();
+    const Totals T = totals(bt);
     const uint32_t total = ctrl->total_pos;
     const uint32_t nwaves = total >> 6;
     const uint32_t lane = lane_id();
-    uint32_t w = PERSISTENT ? 0u : blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
+    uint32_t w = PERSISTENT ? 0u
+                            : blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
         if constexpr (PERSISTENT) {
             // Every lane takes part in the atomic (lane 0 adds 1, the others 0)
@@ -570,7 +606,7 @@ __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, H
             const unsigned long long e = perm[k];
             const uint32_t b = (uint32_t)(e >> 40);
             const uint64_t i = e & ((1ull << 40) - 1);
-            const DevBlock d = get_block(bt, b);
+            const DevBlock d = get_block(bt, T, b);
             live = load_tx(d, i, ks, t);
         }
         const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
@@ -590,8 +626,9 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
 {
     __shared__ unsigned long long part[kWavesPerWG];
     const uint32_t lane = lane_id();
-    for (uint64_t tile = blockIdx.x; tile < bt.total_tiles; tile += gridDim.x) {
-        const DevBlock d = get_block(bt, find_block<0>(bt, tile));
+    const Totals T = totals(bt);
+    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+        const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
         unsigned long long acc = 0;
 #pragma unroll
@@ -618,6 +655,72 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
             if (s) atomicAdd(d.count, s);
         }
         __syncthreads();
+    }
+}
+
+// Device-side plan of a graph replay: copies the block descriptors the host
+// wrote into pinned memory, computes their prefixes in the three index
+// spaces (transactions, tiles, wave tiles), publishes the totals, and clears
+// the per-block counts and the binning control words.  One workgroup.
+constexpr int kPlanWG = 1024;
+__global__ void __launch_bounds__(kPlanWG) k_plan(const DevBlock *__restrict__ src,
+                                                  const uint32_t *__restrict__ src_n,
+                                                  uint32_t max_blocks, DevBlock *__restrict__ table,
+                                                  BatchHdr *__restrict__ hdr, Ctrl *__restrict__ ctrl)
+{
+    __shared__ uint64_t sc[3][kPlanWG];
+    __shared__ uint64_t carry[3];
+    const uint32_t t = threadIdx.x;
+    uint32_t n = *src_n;
+    if (n > max_blocks) n = max_blocks;
+    if (t < 3) carry[t] = 0;
+    if (ctrl && t < kBins) {
+        ctrl->hist[t] = 0;
+        ctrl->cursor[t] = 0;
+        if (t == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += kPlanWG) {
+        const uint32_t b = base + t;
+        DevBlock d{};
+        uint64_t v[3] = {0, 0, 0};
+        if (b < n) {
+            d = src[b];
+            v[0] = d.n;
+            v[1] = (d.n + kTile - 1) / kTile;
+            v[2] = (d.n + 63) / 64;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sc[k][t] = v[k];
+        __syncthreads();
+        for (uint32_t off = 1; off < kPlanWG; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            uint64_t a[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a[k] = t >= off ? sc[k][t - off] : 0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sc[k][t] += a[k];
+            __syncthreads();
+        }
+        if (b < n) {
+            d.tx0 = carry[0] + sc[0][t] - v[0];
+            d.tile0 = carry[1] + sc[1][t] - v[1];
+            d.wave0 = carry[2] + sc[2][t] - v[2];
+            table[b] = d;
+            *d.count = 0;
+        }
+        __syncthreads();
+        if (t == kPlanWG - 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) carry[k] += sc[k][t];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        hdr->n_blocks = n;
+        hdr->total_tx = carry[0];
+        hdr->total_tiles = carry[1];
+        hdr->total_waves = carry[2];
     }
 }
 

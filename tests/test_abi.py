@@ -137,3 +137,37 @@ def test_workspace_size_layout(lib):
     with_mid = lib.ace_verify_workspace_size(ctypes.byref(rks), one, 1, ace.ACE_ORDERED)
     assert with_mid >= ordered + 64 * 1000
     assert lib.ace_verify_workspace_size(None, one, 1, 0) == 0
+
+
+def test_tuning_roundtrip_and_limits(lib):
+    from paper_2603_10242_amd import ace
+    old = ace.get_tuning()
+    assert old["verify_wgs_per_cu"] >= 1 and old["binned_min_tx"] > 0
+    try:
+        ace.set_tuning(verify_wgs_per_cu=4, binned_min_tx=1000)
+        t = ace.get_tuning()
+        assert t["verify_wgs_per_cu"] == 4 and t["binned_min_tx"] == 1000
+        with pytest.raises(ace.AceError):
+            ace.set_tuning(verify_wgs_per_cu=0)
+        with pytest.raises(ace.AceError):
+            ace.set_tuning(aux_wgs_per_cu=65)
+    finally:
+        ace.set_tuning(**old)
+    assert ace.get_tuning() == old
+
+
+def test_graph_argument_errors(lib):
+    from paper_2603_10242_amd import ace
+    ks, keep = _keyset(ace)
+    out = ctypes.c_void_p()
+    assert lib.ace_graph_workspace_size(ctypes.byref(ks), 0, 1000, 0) == 0
+    need = lib.ace_graph_workspace_size(ctypes.byref(ks), 16, 1 << 20, 0)
+    assert need > 12 * (1 << 20)
+    assert lib.ace_graph_create(ctypes.byref(ks), 16, 1 << 20, 0x100000, need - 256, 0,
+                                ctypes.byref(out)) == ace.ACE_ERR_NO_MEMORY
+    assert lib.ace_graph_create(ctypes.byref(ks), 0, 1 << 20, 0x100000, need, 0,
+                                ctypes.byref(out)) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_graph_create(ctypes.byref(ks), 16, 1 << 20, 0x100008, need, 0,
+                                ctypes.byref(out)) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_graph_launch(None, None, 0, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_graph_destroy(None) == ace.ACE_OK
