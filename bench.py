@@ -154,6 +154,129 @@ def bench_batching(args) -> dict:
     }
 
 
+def drive(stream, pool, starts, sizes, arrivals, threads: int = 8):
+    """Open-loop load: request k arrives at arrivals[k] (monotonic seconds) and is
+    submitted then by one of `threads` submitter threads.  Returns the arrival,
+    admit and completion times of every request."""
+    import threading
+    n = len(sizes)
+    tickets = [None] * n
+
+    def submitter(j):
+        for k in range(j, n, threads):
+            delay = arrivals[k] - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            lo, hi = int(starts[k]), int(starts[k] + sizes[k])
+            tickets[k] = stream.submit(pool.msg, pool.off[lo:hi + 1], pool.ids[lo:hi],
+                                       pool.tags[lo:hi])
+
+    ths = [threading.Thread(target=submitter, args=(j,)) for j in range(threads)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    done = np.zeros(n)
+    admit = np.zeros(n)
+    bad = 0
+    for k, t in enumerate(tickets):
+        mask, count = stream.result(t)
+        lo, hi = int(starts[k]), int(starts[k] + sizes[k])
+        if count != int(pool.truth[lo:hi].sum()):
+            bad += 1
+        _, admit[k], done[k] = stream.times(t)
+        stream.release(t)
+    if bad:
+        raise SystemExit("RESULT MISMATCH in %d serving requests" % bad)
+    return np.asarray(arrivals), admit, done
+
+
+def bench_serving(args) -> dict:
+    """Poisson-arriving requests served by the continuous-batching engine and by
+    the plain one-request-per-launch form, offered load swept to saturation."""
+    from paper_2603_10242_amd import workload as W
+    log("generating the serving pool: %d txs over %d identities" % (args.pool, args.n_id_serving))
+    pool = W.config5_pool(n_pool=args.pool, n_id=args.n_id_serving)
+    import torch
+    from paper_2603_10242_amd import ace
+    ace.load()
+    torch.cuda.set_device(0)
+    ks = ace.midstate_keyset(ace.to_device(pool.rev), pool.salt, pool.info)
+    torch.cuda.synchronize()
+    log("midstate cache resident: %.0f MiB" % (ks.mid.numel() * 4 / 2**20))
+    arena = torch.empty(args.arena_gib << 30, dtype=torch.uint8, device="cuda")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([W.SEED_BASE + 5, 3])))
+    mean_size = float(W.serving_request_sizes(200_000).mean())
+    bytes_per_tx = float(pool.lengths().mean()) + 32 + 4 + 8
+
+    def requests(count, seed):
+        sizes = W.serving_request_sizes(count, seed=W.SEED_BASE + 5 + seed)
+        starts = rng.integers(0, pool.n - sizes)
+        return sizes, starts
+
+    out = {}
+    for form, plain in (("continuous", False), ("plain", True)):
+        st = ace.Stream.create(ks, arena, staging_bytes=args.staging_mib << 20,
+                               max_inflight=args.inflight, plain=plain)
+        # saturation: a backlog submitted as fast as the submitters can
+        nsat = args.sat_requests if not plain else max(200, args.sat_requests // 4)
+        sizes, starts = requests(nsat, 1000 + plain)
+        t0 = time.monotonic()
+        arr, adm, done = drive(st, pool, starts, sizes, np.full(nsat, t0))
+        sat = float(sizes.sum()) / (done.max() - t0)
+        out[form] = {"saturation_tx_per_s": sat, "saturation_requests": nsat,
+                     "batches": st.stats()["batches"]}
+        log("%-10s saturation %.3g tx/s (%d requests, %d batches)" % (form, sat, nsat,
+                                                                      st.stats()["batches"]))
+        st.close()
+    ref = out["continuous"]["saturation_tx_per_s"]
+    for form, plain in (("continuous", False), ("plain", True)):
+        st = ace.Stream.create(ks, arena, staging_bytes=args.staging_mib << 20,
+                               max_inflight=args.inflight, plain=plain)
+        points = []
+        for frac in args.loads:
+            rate_tx = frac * ref
+            rate_req = rate_tx / mean_size
+            count = int(min(args.max_requests, max(200, rate_req * args.point_seconds)))
+            sizes, starts = requests(count, int(frac * 1000))
+            gaps = rng.exponential(1.0 / rate_req, size=count)
+            t0 = time.monotonic() + 0.05
+            arr, adm, done = drive(st, pool, starts, sizes, t0 + np.cumsum(gaps))
+            lat = (done - arr) * 1e3
+            span = done.max() - arr.min()
+            points.append({"offered_frac": frac, "offered_tx_per_s": rate_tx,
+                           "achieved_tx_per_s": float(sizes.sum()) / span, "requests": count,
+                           "p50_ms": float(np.percentile(lat, 50)),
+                           "p99_ms": float(np.percentile(lat, 99))})
+            log("%-10s load %.2f: p50 %.3f ms, p99 %.3f ms, %.3g tx/s" % (
+                form, frac, points[-1]["p50_ms"], points[-1]["p99_ms"],
+                points[-1]["achieved_tx_per_s"]))
+        out[form]["sweep"] = points
+        out[form]["stats"] = st.stats()
+        st.close()
+    half = [p for p in out["continuous"]["sweep"] if abs(p["offered_frac"] - 0.5) < 1e-9]
+    return {
+        "metric": METRIC,
+        "value": out["continuous"]["saturation_tx_per_s"],
+        "unit": "attestations/s",
+        "n_gpus": 1, "steps": len(args.loads), "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson requests of lognormal(1,000, 1.5) txs in "
+                               "[1, 50,000], requests cut from a %d-tx pool" % pool.n,
+                   "n_id": pool.n_id, "ids": "zipf 1.1", "keys": "resident midstates",
+                   "arena_gib": args.arena_gib, "staging_mib": args.staging_mib,
+                   "max_inflight": args.inflight, "mean_request_txs": mean_size,
+                   "latency": "scheduled arrival to bitmask in host memory"},
+        "forms": out,
+        "saturation_speedup_vs_plain": ref / out["plain"]["saturation_tx_per_s"],
+        "p99_ms": half[0]["p99_ms"] if half else None,
+        "pcie_ceiling_tx_per_s": 64e9 / bytes_per_tx,
+        "device": torch.cuda.get_device_name(0),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,8 +288,19 @@ def main() -> int:
     ap.add_argument("--keys", choices=["recomputed", "midstate"], default="recomputed",
                     help="derive every identity's key in the step, or use resident midstates")
     ap.add_argument("--mode", choices=["binned", "binned-persistent", "ordered"], default="binned")
-    ap.add_argument("--workload", choices=["sweep", "batching"], default="sweep",
-                    help="sweep: the throughput sweep (default); batching: 256 uneven blocks")
+    ap.add_argument("--workload", choices=["sweep", "batching", "serving"], default="sweep",
+                    help="sweep: the throughput sweep (default); batching: 256 uneven blocks; "
+                         "serving: Poisson requests through the serving engine")
+    ap.add_argument("--pool", type=int, default=4 << 20, help="serving: transactions in the pool")
+    ap.add_argument("--n-id-serving", type=int, default=4 << 20, help="serving: identities")
+    ap.add_argument("--arena-gib", type=int, default=8, help="serving: device arena")
+    ap.add_argument("--staging-mib", type=int, default=2048, help="serving: pinned staging")
+    ap.add_argument("--inflight", type=int, default=4, help="serving: batches in flight")
+    ap.add_argument("--sat-requests", type=int, default=4000)
+    ap.add_argument("--max-requests", type=int, default=20000)
+    ap.add_argument("--point-seconds", type=float, default=1.5)
+    ap.add_argument("--loads", type=float, nargs="+",
+                    default=[0.1, 0.18, 0.32, 0.5, 0.75, 0.9, 1.1, 1.5])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run three plain device copies of this many bytes (a reference "
                          "for scaling hardware byte counters)")
@@ -182,6 +316,9 @@ def main() -> int:
 
     if args.workload == "batching":
         print(json.dumps(bench_batching(args)), flush=True)
+        return 0
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
         return 0
 
     from paper_2603_10242_amd import workload as W

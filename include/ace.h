@@ -188,6 +188,77 @@ ACE_API int ace_graph_launch(ace_graph *g, const ace_block *blocks, uint32_t n_b
 ACE_API int ace_graph_destroy(ace_graph *g);
 
 /*
+ * Serving (continuous batching).  ace_stream_create starts a server thread
+ * that owns the device arena `d_arena` (caller-allocated, 256-byte aligned)
+ * and `staging_bytes` of pinned host memory (allocated here, once).
+ * ace_verify_stream submits one request -- a block of transactions in host
+ * memory -- and returns a ticket.  The request is copied into staging before
+ * the call returns, so the caller may reuse its input buffers at once; the
+ * outputs h_bitmask_out ([ceil(n_tx/32)] words) and h_count_out are written
+ * when the ticket completes and must stay valid until then.  Queued requests
+ * are admitted into a batch as soon as arena space and one of max_inflight
+ * batch slots are free; each batch is one multi-block verify pass on its own
+ * HIP stream, so a batch admitted while others run overlaps them on the
+ * device.  A request's result does not depend on what it is batched with.
+ *   keys   ACE_KEYS_MIDSTATE (the cache stays where it is), or ACE_KEYS_REV:
+ *          the midstates are derived once into the front of the arena and
+ *          stay resident.
+ *   flags  ACE_STREAM_PLAIN: one request per launch, in arrival order, each
+ *          finished before the next starts (the reference form).
+ * ace_verify_stream errors: ACE_ERR_TOO_LARGE when the request can never fit
+ * staging or arena (with its workspace); with ACE_NONBLOCK, ACE_ERR_AGAIN
+ * when staging is full right now (without it the call waits for room).
+ * ace_stream_poll returns ACE_OK when done, ACE_ERR_AGAIN while pending
+ * (wait = 0), or the request's error.  ace_stream_ticket_times gives the
+ * submit, admit and completion times in seconds of the monotonic clock
+ * (CLOCK_MONOTONIC).
+ * ace_stream_release forgets a completed ticket.  ace_stream_destroy finishes
+ * every queued and running request, then frees the engine (not the arena).
+ */
+#define ACE_NONBLOCK 0x1u
+#define ACE_STREAM_PLAIN 0x1u
+
+typedef struct ace_stream ace_stream;
+typedef struct {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t failed;
+    uint64_t batches;
+    uint64_t max_batch_requests;
+    uint64_t pending;
+    uint64_t arena_peak_bytes;
+    uint64_t arena_capacity_bytes;
+} ace_stream_stats;
+
+ACE_API int ace_stream_create(const ace_keyset *keys, void *d_arena, size_t arena_bytes,
+                              size_t staging_bytes, uint32_t max_inflight, uint32_t flags,
+                              ace_stream **out);
+ACE_API int ace_verify_stream(ace_stream *s, const uint8_t *h_msg, const uint64_t *h_off,
+                              const uint32_t *h_id, const uint8_t *h_tag, uint64_t n_tx,
+                              uint32_t *h_bitmask_out, uint64_t *h_count_out, uint32_t flags,
+                              uint64_t *ticket_out);
+ACE_API int ace_stream_poll(ace_stream *s, uint64_t ticket, int wait);
+ACE_API int ace_stream_ticket_times(ace_stream *s, uint64_t ticket, double *submit_s,
+                                    double *admit_s, double *done_s);
+ACE_API int ace_stream_release(ace_stream *s, uint64_t ticket);
+ACE_API int ace_stream_get_stats(ace_stream *s, ace_stream_stats *out);
+ACE_API int ace_stream_destroy(ace_stream *s);
+
+/*
+ * Test hook: the same engine with a host backend -- the "arena" is host memory
+ * allocated here, and each batch's blocks are verified by calling `fn` (for
+ * example a CPU reference) -- so the queue, admission and retirement logic
+ * runs without a GPU.  fail_after = k > 0 makes the k-th batch fail as a
+ * device error would; only that batch's requests fail.
+ */
+typedef int (*ace_host_verify_fn)(void *user, const uint8_t *msg, const uint64_t *off,
+                                  const uint32_t *id, const uint8_t *tag, uint64_t n_tx,
+                                  uint32_t *bitmask_out, uint64_t *count_out);
+ACE_API int ace_stream_create_host(ace_host_verify_fn fn, void *user, size_t arena_bytes,
+                                   size_t staging_bytes, uint32_t max_inflight, uint32_t flags,
+                                   uint32_t fail_after, ace_stream **out);
+
+/*
  * Stage timing (tracing).  While enabled on the calling thread, every
  * ace_verify_batch call records HIP events on its own stream around its
  * stages: key derivation, length binning (count, scan, scatter), the verify

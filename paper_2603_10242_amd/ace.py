@@ -308,3 +308,156 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------ serving
+ACE_NONBLOCK = 0x1
+ACE_STREAM_PLAIN = 0x1
+
+
+class ace_stream_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "batches",
+                                                "max_batch_requests", "pending",
+                                                "arena_peak_bytes", "arena_capacity_bytes")]
+
+
+HOST_VERIFY_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _stream_protos(lib):
+    if getattr(lib, "_stream_protos", False):
+        return
+    vp, sz, u32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint64
+    lib.ace_stream_create.argtypes = [ctypes.POINTER(ace_keyset), vp, sz, sz, u32, u32,
+                                      ctypes.POINTER(vp)]
+    lib.ace_stream_create_host.argtypes = [HOST_VERIFY_FN, vp, sz, sz, u32, u32, u32,
+                                           ctypes.POINTER(vp)]
+    lib.ace_verify_stream.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, u32, ctypes.POINTER(u64)]
+    lib.ace_stream_poll.argtypes = [vp, u64, ctypes.c_int]
+    lib.ace_stream_ticket_times.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]
+    lib.ace_stream_release.argtypes = [vp, u64]
+    lib.ace_stream_get_stats.argtypes = [vp, ctypes.POINTER(ace_stream_stats)]
+    lib.ace_stream_destroy.argtypes = [vp]
+    lib._stream_protos = True
+
+
+class Ticket:
+    """One submitted request: its id and the host arrays its outputs land in."""
+
+    def __init__(self, ticket: int, n: int, mask: np.ndarray, count: np.ndarray):
+        self.id = ticket
+        self.n = n
+        self.mask = mask
+        self.count = count
+
+
+class Stream:
+    """ace_stream_*: continuous-batching verification of requests from host memory."""
+
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = list(keep)
+
+    @classmethod
+    def create(cls, keyset: DeviceKeyset, arena: torch.Tensor, staging_bytes: int,
+               max_inflight: int = 4, plain: bool = False) -> "Stream":
+        lib = load()
+        _stream_protos(lib)
+        ks, keep = keyset.struct()
+        h = ctypes.c_void_p()
+        _check(lib.ace_stream_create(ctypes.byref(ks), _ptr(arena), arena.numel(), staging_bytes,
+                                     max_inflight, ACE_STREAM_PLAIN if plain else 0, ctypes.byref(h)))
+        return cls(h, [keep, arena, keyset])
+
+    @classmethod
+    def create_host(cls, verify, arena_bytes: int, staging_bytes: int, max_inflight: int = 4,
+                    plain: bool = False, fail_after: int = 0) -> "Stream":
+        """Host backend for tests: verify(msg, off, ids, tags) -> (bitmask u32[], count)."""
+        lib = load()
+        _stream_protos(lib)
+
+        def cb(user, msg, off, ids, tag, n, mask_out, count_out):
+            try:
+                n = int(n)
+                o = np.ctypeslib.as_array(ctypes.cast(off, ctypes.POINTER(ctypes.c_uint64)),
+                                          (n + 1,)).copy()
+                span = int(o.max()) if n else 0
+                m = (np.ctypeslib.as_array(ctypes.cast(msg, ctypes.POINTER(ctypes.c_uint8)),
+                                           (span,)).copy() if span else np.zeros(0, np.uint8))
+                i = (np.ctypeslib.as_array(ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32)),
+                                           (n,)).copy() if n else np.zeros(0, np.uint32))
+                t = (np.ctypeslib.as_array(ctypes.cast(tag, ctypes.POINTER(ctypes.c_uint8)),
+                                           (n, 32)).copy() if n else np.zeros((0, 32), np.uint8))
+                bm, c = verify(m, o, i, t)
+                if n:
+                    out = np.ctypeslib.as_array(ctypes.cast(mask_out, ctypes.POINTER(ctypes.c_uint32)),
+                                                ((n + 31) // 32,))
+                    out[:] = bm
+                ctypes.cast(count_out, ctypes.POINTER(ctypes.c_uint64))[0] = int(c)
+                return 0
+            except Exception:  # reported to the engine as a device failure
+                return -1
+
+        fn = HOST_VERIFY_FN(cb)
+        h = ctypes.c_void_p()
+        _check(lib.ace_stream_create_host(fn, None, arena_bytes, staging_bytes, max_inflight,
+                                          ACE_STREAM_PLAIN if plain else 0, fail_after,
+                                          ctypes.byref(h)))
+        return cls(h, [fn])
+
+    def submit(self, msg: np.ndarray, off: np.ndarray, ids: np.ndarray, tags: np.ndarray,
+               nonblock: bool = False) -> Ticket:
+        n = int(ids.shape[0])
+        msg = np.ascontiguousarray(msg, np.uint8)
+        off = np.ascontiguousarray(off, np.uint64)
+        ids = np.ascontiguousarray(ids, np.uint32)
+        tags = np.ascontiguousarray(tags, np.uint8)
+        mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
+        count = np.zeros(1, np.uint64)
+        t = ctypes.c_uint64()
+        _check(load().ace_verify_stream(self._h, msg.ctypes.data if msg.size else None,
+                                        off.ctypes.data, ids.ctypes.data if n else None,
+                                        tags.ctypes.data if n else None, n, mask.ctypes.data,
+                                        count.ctypes.data, ACE_NONBLOCK if nonblock else 0,
+                                        ctypes.byref(t)))
+        return Ticket(t.value, n, mask, count)
+
+    def poll(self, ticket: Ticket, wait: bool = True) -> bool:
+        rc = load().ace_stream_poll(self._h, ticket.id, 1 if wait else 0)
+        if rc == ACE_ERR_AGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def result(self, ticket: Ticket) -> tuple[np.ndarray, int]:
+        self.poll(ticket, True)
+        return ticket.mask[: (ticket.n + 31) // 32].copy(), int(ticket.count[0])
+
+    def times(self, ticket: Ticket) -> tuple[float, float, float]:
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        load().ace_stream_ticket_times(self._h, ticket.id, ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def release(self, ticket: Ticket) -> None:
+        _check(load().ace_stream_release(self._h, ticket.id))
+
+    def stats(self) -> dict:
+        st = ace_stream_stats()
+        _check(load().ace_stream_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ace_stream_stats._fields_}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(load().ace_stream_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

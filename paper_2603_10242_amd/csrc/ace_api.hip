@@ -150,7 +150,7 @@ struct Plan {
     uint64_t total_waves;
     uint64_t max_pos;  // upper bound of bin-order positions
     // workspace layout (byte offsets)
-    size_t off_ctrl, off_hdr, off_descs, off_mid, off_perm, off_posof, off_vperm, bytes;
+    size_t off_ctrl, off_hdr, off_descs, off_mid, off_perm, off_rec, off_posof, off_vperm, bytes;
 };
 
 int check_keyset(const ace_keyset *keys, uint32_t flags, Plan &p)
@@ -232,6 +232,7 @@ void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t 
     p.off_descs = o; o = align_up(o + (table ? (size_t)n_blocks * sizeof(DevBlock) : 0), 256);
     p.off_mid = o;   o = align_up(o + (p.rev && !p.per_tx ? 64ull * keys->n_id : 0), 256);
     p.off_perm = o;  o = align_up(o + (binned ? 8ull * p.max_pos : 0), 256);
+    p.off_rec = o;   o = align_up(o + (binned ? sizeof(TxRec) * p.max_pos : 0), 256);
     p.off_posof = o; o = align_up(o + (binned ? 4ull * total : 0), 256);
     p.off_vperm = o; o = align_up(o + (binned ? 4ull * (p.max_pos / 32 + 2) : 0), 256);
     p.bytes = o;
@@ -331,31 +332,33 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     }
 
     unsigned long long *perm = reinterpret_cast<unsigned long long *>(ws + p.off_perm);
+    TxRec *rec = reinterpret_cast<TxRec *>(ws + p.off_rec);
     uint32_t *pos_of = reinterpret_cast<uint32_t *>(ws + p.off_posof);
     uint32_t *vperm = reinterpret_cast<uint32_t *>(ws + p.off_vperm);
     const uint64_t tiles_bound = graph ? (p.total_tx + kTile - 1) / kTile + p.n_blocks : p.total_tiles;
     const unsigned gtiles = grid_for(tiles_bound, 1, tn.aux_wgs_per_cu * cus);
 
-    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl);
+    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id);
     if ((rc = launch_status("k_bin_count launch"))) return rc;
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
     if ((rc = launch_status("k_bin_scan launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, perm, pos_of);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm, rec,
+                       pos_of);
     if ((rc = launch_status("k_bin_scatter launch"))) return rc;
     prof_mark(prof, 2, s);
 
     if (p.persistent) {
         const unsigned g = tn.verify_wgs_per_cu * cus;
         if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
         else
-            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
     } else {
         const unsigned g = grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
         if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
         else
-            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, vperm);
+            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
     }
     if ((rc = launch_status("k_verify_binned launch"))) return rc;
     prof_mark(prof, 3, s);
@@ -676,3 +679,6 @@ ACE_API int ace_graph_destroy(ace_graph *g)
 }
 
 }  // extern "C"
+
+// Serving engine (ace_verify_stream and friends), same translation unit.
+#include "ace_stream.hip"

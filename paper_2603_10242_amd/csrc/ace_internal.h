@@ -80,6 +80,17 @@ struct HkdfPrep {
     uint32_t info_blocks;
 };
 
+// One transaction in bin order, written by the scatter pass so that the
+// verify kernel reads contiguous records instead of gathering offsets and
+// identities from scattered lines.
+constexpr uint32_t kRecWide = 0xFFFFFFFFu;     // len: too long for 32 bits, re-read the offsets
+constexpr uint32_t kRecInvalid = 0xFFFFFFFFu;  // id: the transaction cannot be valid
+struct TxRec {
+    uint64_t addr;  // address of the first message byte
+    uint32_t len;   // message length, or kRecWide
+    uint32_t id;    // identity index, or kRecInvalid
+};
+
 struct KeySource {
     const uint32_t *mid;   // [n_id][16] midstates, or NULL when keys come from rev
     const uint8_t *rev;    // [n_id][32] root entropy (per-transaction derivation)

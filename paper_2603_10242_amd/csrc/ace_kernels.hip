@@ -309,9 +309,13 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
         derive_lane(live, rv, *prep, key, S, opad);
     } else {
         if (live) {
+            // both halves of the 64-byte row at once: one cache line, fetched once
             const U4 a = load16(t.mid), b = load16(t.mid + 4);
+            const U4 c = load16(t.mid + 8), e = load16(t.mid + 12);
             S.h[0] = a.x; S.h[1] = a.y; S.h[2] = a.z; S.h[3] = a.w;
             S.h[4] = b.x; S.h[5] = b.y; S.h[6] = b.z; S.h[7] = b.w;
+            opad.h[0] = c.x; opad.h[1] = c.y; opad.h[2] = c.z; opad.h[3] = c.w;
+            opad.h[4] = e.x; opad.h[5] = e.y; opad.h[6] = e.z; opad.h[7] = e.w;
         }
     }
 
@@ -375,13 +379,7 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
                 }
             } else {
                 // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
-                if constexpr (PER_TX_KEYS) {
-                    in = opad;
-                } else {
-                    const U4 a = load16(t.mid + 8), c = load16(t.mid + 12);
-                    in.h[0] = a.x; in.h[1] = a.y; in.h[2] = a.z; in.h[3] = a.w;
-                    in.h[4] = c.x; in.h[5] = c.y; in.h[6] = c.z; in.h[7] = c.w;
-                }
+                in = opad;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) W[i] = S.h[i];
                 W[8] = 0x80000000u;
@@ -474,13 +472,14 @@ __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
     }
 }
 
-__device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i)
+// Length used for binning: transactions that cannot be valid hash nothing.
+__device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i, uint32_t n_id)
 {
     const uint64_t a = d.off[i], e = d.off[i + 1];
-    return a <= e ? e - a : 0;
+    return (a <= e && d.id[i] < n_id) ? e - a : 0;
 }
 
-__global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl)
+__global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl, uint32_t n_id)
 {
     __shared__ uint32_t h[kBins];
     if (threadIdx.x < kBins) h[threadIdx.x] = 0;
@@ -491,7 +490,7 @@ __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl)
         const uint64_t i0 = (tile - d.tile0) * kTile;
         for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
             const uint64_t i = i0 + k;
-            if (i < d.n) atomicAdd(&h[bin_of_length(tx_length(d, i))], 1u);
+            if (i < d.n) atomicAdd(&h[bin_of_length(tx_length(d, i, n_id))], 1u);
         }
     }
     __syncthreads();
@@ -517,8 +516,9 @@ __global__ void k_bin_scan(Ctrl *ctrl)
     if (o == kBins - 1) ctrl->total_pos = start + pad;
 }
 
-__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
+__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint32_t n_id,
                                                      unsigned long long *__restrict__ perm,
+                                                     TxRec *__restrict__ rec,
                                                      uint32_t *__restrict__ pos_of)
 {
     constexpr int kPer = kTile / kWG;
@@ -532,12 +532,20 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
         if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
         __syncthreads();
         uint32_t bins[kPer], rank[kPer];
+        TxRec r[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
             bins[k] = kBins;
             if (i < d.n) {
-                bins[k] = bin_of_length(tx_length(d, i));
+                const uint64_t a = d.off[i], e = d.off[i + 1];
+                const uint32_t who = d.id[i];
+                const bool ok = a <= e && who < n_id;
+                const uint64_t L = ok ? e - a : 0;
+                r[k].addr = reinterpret_cast<uint64_t>(d.msg + a);
+                r[k].len = L >= kRecWide ? kRecWide : (uint32_t)L;
+                r[k].id = ok ? who : kRecInvalid;
+                bins[k] = bin_of_length(L);
                 rank[k] = atomicAdd(&cnt[bins[k]], 1u);
             }
         }
@@ -551,6 +559,7 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
                 const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
                 const uint32_t pos = base[bins[k]] + rank[k];
                 perm[pos] = ((unsigned long long)b << 40) | i;
+                rec[pos] = r[k];
                 pos_of[d.tx0 + i] = pos;
             }
         }
@@ -566,6 +575,7 @@ template <bool PER_TX_KEYS, bool PERSISTENT>
 __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
+                                                       const TxRec *__restrict__ rec,
                                                        uint32_t *__restrict__ vperm)
 {
     __shared__ HkdfPrep prep;
@@ -604,10 +614,20 @@ __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, H
         bool live = false;
         if (active) {
             const unsigned long long e = perm[k];
+            const TxRec r = rec[k];
             const uint32_t b = (uint32_t)(e >> 40);
             const uint64_t i = e & ((1ull << 40) - 1);
-            const DevBlock d = get_block(bt, T, b);
-            live = load_tx(d, i, ks, t);
+            if (r.len == kRecWide) {
+                live = load_tx(get_block(bt, T, b), i, ks, t);  // message of 4 GiB or more
+            } else {
+                live = r.id != kRecInvalid;
+                const uint32_t who = live ? r.id : 0u;
+                t.msg = reinterpret_cast<const uint8_t *>(r.addr);
+                t.L = r.len;
+                t.mid = ks.mid ? ks.mid + 16ull * who : nullptr;
+                t.rev = ks.rev ? ks.rev + 32ull * who : nullptr;
+                t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) + 32ull * i;
+            }
         }
         const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
@@ -735,12 +755,16 @@ __global__ void k_put_descs(DevBlock *table, DescChunk c)
 template __global__ void k_verify_ordered<false>(Batch, KeySource, HkdfParams);
 template __global__ void k_verify_ordered<true>(Batch, KeySource, HkdfParams);
 template __global__ void k_verify_binned<false, false>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                       const unsigned long long *, uint32_t *);
+                                                       const unsigned long long *, const TxRec *,
+                                                       uint32_t *);
 template __global__ void k_verify_binned<false, true>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                      const unsigned long long *, uint32_t *);
+                                                      const unsigned long long *, const TxRec *,
+                                                      uint32_t *);
 template __global__ void k_verify_binned<true, false>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                      const unsigned long long *, uint32_t *);
+                                                      const unsigned long long *, const TxRec *,
+                                                      uint32_t *);
 template __global__ void k_verify_binned<true, true>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                     const unsigned long long *, uint32_t *);
+                                                     const unsigned long long *, const TxRec *,
+                                                     uint32_t *);
 
 }  // namespace ace

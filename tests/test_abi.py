@@ -130,9 +130,10 @@ def test_workspace_size_layout(lib):
     ordered = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_ORDERED)
     binned = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_BUCKETED)
     assert 0 < ordered < 4096
-    # binned: 8 B permutation + 4 B position + 1 bit per transaction, plus padding
-    assert binned >= ordered + 12 * 1_000_000
-    assert binned < ordered + 13 * 1_000_000 + 64 * 1024
+    # binned: 8 B permutation + 16 B record + 4 B position + 1 bit per transaction,
+    # plus 64 bins of padding
+    assert binned >= ordered + 28 * 1_000_000
+    assert binned < ordered + 29 * 1_000_000 + 128 * 1024
     rks, rkeep = _keyset(ace, kind=1, rev=0x7000, n_id=1000)
     with_mid = lib.ace_verify_workspace_size(ctypes.byref(rks), one, 1, ace.ACE_ORDERED)
     assert with_mid >= ordered + 64 * 1000
@@ -162,7 +163,7 @@ def test_graph_argument_errors(lib):
     out = ctypes.c_void_p()
     assert lib.ace_graph_workspace_size(ctypes.byref(ks), 0, 1000, 0) == 0
     need = lib.ace_graph_workspace_size(ctypes.byref(ks), 16, 1 << 20, 0)
-    assert need > 12 * (1 << 20)
+    assert need > 28 * (1 << 20)
     assert lib.ace_graph_create(ctypes.byref(ks), 16, 1 << 20, 0x100000, need - 256, 0,
                                 ctypes.byref(out)) == ace.ACE_ERR_NO_MEMORY
     assert lib.ace_graph_create(ctypes.byref(ks), 0, 1 << 20, 0x100000, need, 0,
