@@ -42,6 +42,36 @@ def compressions(lengths: np.ndarray) -> int:
     return int(((lengths + 9 + 63) // 64 + 1).sum())
 
 
+KERNEL_SOURCES = ("paper_2603_10242_amd/csrc/ace_kernels.hip",
+                  "paper_2603_10242_amd/csrc/sha256_gfx950.h",
+                  "paper_2603_10242_amd/csrc/ace_internal.h")
+COUNTERS = "profiles/k_verify_binned_sweep16M_hbm_counters.md"
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per launch of the verify kernel from the committed FETCH_SIZE and
+    WRITE_SIZE summary, or None when the kernels changed after it was taken."""
+    try:
+        text = open(os.path.join(ROOT, COUNTERS)).read()
+    except OSError:
+        return None
+    fields = dict(l.strip().split(": ", 1) for l in text.splitlines() if ": " in l.strip()
+                  and l.strip().split(": ", 1)[0] in ("kernel_sources_sha256",
+                                                       "traffic_bytes_per_launch"))
+    if fields.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, seconds: float) -> dict:
     """The CPU oracle as it stands on this host: all keys, then a prefix sample of txs."""
     import oracle
@@ -424,7 +454,9 @@ def main() -> int:
             "peak": PEAK_INT32_TOPS,
             "unit": "T int32 lane-instr/s",
             "frac": achieved / PEAK_INT32_TOPS,
-            "traffic": None,
+            "traffic": counter_traffic() if (args.n == 16 << 20 and args.mode == "binned"
+                                              and args.keys == "recomputed"
+                                              and args.ids == "uniform") else None,
             "per_launch": "%d compressions x %d VALU instr" % (verify_comp, I_REF),
             "avg_ms": verify_s * 1e3,
         },
