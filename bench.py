@@ -126,9 +126,10 @@ def bench_batching(args) -> dict:
     log("generating the batching workload (256 blocks)")
     w = W.config4()
     import torch
-    from paper_2603_10242_amd import ace
+    from paper_2603_10242_amd import ace, autotune
     ace.load()
     torch.cuda.set_device(0)
+    autotune.apply_saved()
     edges = np.concatenate([[0], np.cumsum(w.block_sizes)])
     d_msg = ace.to_device(w.msg)
     blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
@@ -228,9 +229,10 @@ def bench_serving(args) -> dict:
     log("generating the serving pool: %d txs over %d identities" % (args.pool, args.n_id_serving))
     pool = W.config5_pool(n_pool=args.pool, n_id=args.n_id_serving)
     import torch
-    from paper_2603_10242_amd import ace
+    from paper_2603_10242_amd import ace, autotune
     ace.load()
     torch.cuda.set_device(0)
+    autotune.apply_saved()
     ks = ace.midstate_keyset(ace.to_device(pool.rev), pool.salt, pool.info)
     torch.cuda.synchronize()
     log("midstate cache resident: %.0f MiB" % (ks.mid.numel() * 4 / 2**20))
@@ -361,10 +363,11 @@ def main() -> int:
         % (L.sum() / 1e9, verify_comp / w.n))
 
     import torch
-    from paper_2603_10242_amd import ace
+    from paper_2603_10242_amd import ace, autotune
     ace.load()
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
+    tuned = autotune.apply_saved()
     if args.copy_bytes:
         src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -472,6 +475,8 @@ def main() -> int:
                             if derive_comp and derive_s > 0 else None),
         "hbm_gbs_algorithmic_verify": verify_bytes / verify_s / 1e9,
         "device": dev_name,
+        "tuning": ace.get_tuning(),
+        "tuning_source": "autotuned" if tuned else "library defaults",
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (about %.0f s)" % args.cpu_seconds)

@@ -1,0 +1,161 @@
+"""Autotuner for the launch shapes of libace.so.
+
+Measures, on the device at hand, the candidates the library can run and
+installs the fastest through ace_set_tuning:
+
+* binned_min_tx: the batch size from which binning by block count beats the
+  in-order kernel (the binning passes cost a few launches; below this size
+  they do not pay);
+* verify_wgs_per_cu ("tiles per CU"): workgroups per CU of the persistent
+  verify kernel (and of the graph's in-order one), and whether the open mode
+  should use the persistent kernel at all (auto_persistent);
+* aux_wgs_per_cu: workgroups per CU of the binning and finalize passes.
+
+One transaction always owns one lane: SHA-256 is a Merkle-Damgard chain, so
+the blocks of one message cannot be split across lanes, and the candidates
+for lanes-per-message > 1 reduce to one lane doing the work while the others
+wait.  The result is stored as JSON keyed by GPU architecture and CU count
+(``tuning_<arch>_<cus>cu.json`` next to this file) and applied by
+``apply_saved()``.
+
+Run: python -m paper_2603_10242_amd.autotune
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def device_key() -> tuple[str, int]:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return arch, int(p.multi_processor_count)
+
+
+def tuning_path(arch: str, cus: int) -> str:
+    return os.path.join(HERE, "tuning_%s_%dcu.json" % (arch, cus))
+
+
+def apply_saved(verbose: bool = False) -> dict | None:
+    """Installs the saved tuning for this device, if there is one."""
+    from . import ace
+    try:
+        arch, cus = device_key()
+    except Exception:
+        return None
+    path = tuning_path(arch, cus)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        saved = json.load(fh)
+    ace.set_tuning(**saved["tuning"])
+    if verbose:
+        print("autotune: applied %s" % path, file=sys.stderr)
+    return saved["tuning"]
+
+
+def _time(fn, reps: int = 5) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        best = min(best, s.elapsed_time(e))
+    return best
+
+
+def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20,
+        write: bool = True, log=print, out_dir: str | None = None) -> dict:
+    import torch
+
+    from . import ace
+    from . import workload as W
+
+    ace.load()
+    torch.cuda.set_device(0)
+    arch, cus = device_key()
+    default = ace.get_tuning()
+    log("autotune on %s (%d CUs)" % (arch, cus))
+    w = W.config3(n=max(max(sizes), big), n_id=1 << 18)
+    ks = ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info)
+    d_msg = ace.to_device(w.msg)
+    meas = []
+
+    def block(n):
+        return ace.upload_block(None, w.off[: n + 1], w.ids[:n], w.tags[:n], msg_dev=d_msg)
+
+    # 1. in-order vs binned by batch size
+    crossover = None
+    for n in sizes:
+        blk = block(n)
+        t_ord = _time(lambda: ace.verify_batch(ks, [blk], flags=ace.ACE_ORDERED))
+        t_bin = _time(lambda: ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED))
+        meas.append({"n": n, "ordered_ms": t_ord, "binned_ms": t_bin})
+        log("n=%8d ordered %.3f ms, binned %.3f ms" % (n, t_ord, t_bin))
+        if crossover is None and t_bin < t_ord:
+            crossover = n
+    binned_min = crossover if crossover is not None else (1 << 62)
+
+    # 2. persistent verify: workgroups per CU, against the dispatcher-scheduled kernel
+    blk = block(big)
+    t_plain = _time(lambda: ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED))
+    best = (t_plain, None)
+    for wpc in (1, 2, 4, 8, 16):
+        ace.set_tuning(verify_wgs_per_cu=wpc)
+        t = _time(lambda: ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED | ace.ACE_PERSISTENT))
+        meas.append({"n": big, "persistent_wgs_per_cu": wpc, "ms": t})
+        log("persistent %2d WG/CU: %.3f ms (dispatcher-scheduled %.3f ms)" % (wpc, t, t_plain))
+        if t < best[0]:
+            best = (t, wpc)
+    # graphs always use the persistent kernel: keep its best shape even if the
+    # dispatcher-scheduled kernel wins in eager calls
+    best_wpc = best[1] if best[1] is not None else min(
+        (m for m in meas if "persistent_wgs_per_cu" in m), key=lambda m: m["ms"])["persistent_wgs_per_cu"]
+
+    # 3. binning and finalize passes: workgroups per CU
+    ace.set_tuning(verify_wgs_per_cu=best_wpc)
+    best_aux = (float("inf"), default["aux_wgs_per_cu"])
+    for apc in (2, 4, 8, 16):
+        ace.set_tuning(aux_wgs_per_cu=apc)
+        t = _time(lambda: ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED))
+        meas.append({"n": big, "aux_wgs_per_cu": apc, "ms": t})
+        log("aux %2d WG/CU: %.3f ms" % (apc, t))
+        if t < best_aux[0]:
+            best_aux = (t, apc)
+
+    tuning = {"binned_min_tx": int(binned_min), "verify_wgs_per_cu": int(best_wpc),
+              "aux_wgs_per_cu": int(best_aux[1]), "auto_persistent": int(best[1] is not None)}
+    ace.set_tuning(**tuning)
+    result = {"arch": arch, "cus": cus, "tuning": tuning, "lanes_per_message": 1,
+              "measured": meas, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if write:
+        path = tuning_path(arch, cus)
+        if out_dir:
+            path = os.path.join(out_dir, os.path.basename(path))
+        with open(path, "w") as fh:
+            json.dump(result, fh, indent=1)
+        log("wrote %s" % path)
+    return result
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="measure and store the launch tuning")
+    ap.add_argument("--out", default=None, help="directory for the JSON (default: the package)")
+    a = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+    out = run(log=lambda m: print(m, file=sys.stderr, flush=True), out_dir=a.out)
+    print(json.dumps(out["tuning"]))
