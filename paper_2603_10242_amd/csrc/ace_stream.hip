@@ -78,9 +78,9 @@ class RangeAlloc {
     size_t cap_ = 0, used_ = 0, peak_ = 0;
 };
 
-// Byte layout of one request (identical in staging and in the arena).
+// Byte layout of one request's inputs (identical in staging and in the arena).
 struct ReqLayout {
-    size_t off_off, off_id, off_tag, off_msg, off_mask, off_count, in_bytes, bytes;
+    size_t off_off, off_id, off_tag, off_msg, in_bytes, mask_bytes, out_bytes;
     static ReqLayout of(uint64_t n, size_t msg_bytes)
     {
         ReqLayout l;
@@ -90,9 +90,9 @@ struct ReqLayout {
         l.off_tag = o;   o = align_up(o + 32 * n, 256);
         l.off_msg = o;   o = align_up(o + msg_bytes + 4, 256);
         l.in_bytes = o;
-        l.off_mask = o;  o = align_up(o + 4 * ((n + 31) / 32), 256);
-        l.off_count = o; o = align_up(o + 8, 256);
-        l.bytes = o;
+        // outputs live in the batch's result area: bitmask words, then the count
+        l.mask_bytes = align_up(4 * ((n + 31) / 32), 8);
+        l.out_bytes = l.mask_bytes + 8;
         return l;
     }
 };
@@ -101,8 +101,8 @@ struct Request {
     uint64_t ticket;
     uint64_t n;
     ReqLayout lay;
-    size_t stage_off;
-    size_t dev_off = 0;
+    size_t stage_off;     // inputs in staging
+    size_t out_rel = 0;   // outputs within the batch's result area
     uint32_t *h_mask;
     uint64_t *h_count;
     double t_submit, t_admit = 0, t_done = 0;
@@ -258,6 +258,9 @@ double now_s()
 }
 
 constexpr uint32_t kMaxBatchRequests = 4096;
+constexpr uint64_t kMaxBatchTx = 16ull << 20;  // keeps one batch's latency bounded
+// per-slot pinned result buffer: every request's bitmask (8-byte padded) and count
+constexpr size_t kResultBytes = kMaxBatchTx / 8 + 16ull * kMaxBatchRequests + 4096;
 
 }  // namespace
 
@@ -283,7 +286,8 @@ struct ace_stream {
         bool busy = false;
         bool launching = false;
         std::vector<Request *> members;
-        size_t ws_off = 0, ws_bytes = 0;
+        size_t arena_off = 0, arena_bytes = 0;  // inputs, outputs and workspace of the batch
+        uint8_t *result = nullptr;              // pinned host copy of the batch's outputs
     };
     std::vector<Slot> slot;
     ace_stream_stats stats{};
@@ -293,6 +297,15 @@ struct ace_stream {
 namespace {
 
 // Server side: retire finished batches (lock held).
+void release_batch(ace_stream *s, ace_stream::Slot &sl)
+{
+    for (Request *r : sl.members) s->stage_alloc.release(r->stage_off, r->lay.in_bytes);
+    if (sl.arena_bytes) s->arena_alloc.release(sl.arena_off, sl.arena_bytes);
+    sl.members.clear();
+    sl.arena_bytes = 0;
+    sl.busy = false;
+}
+
 void retire(ace_stream *s, bool block)
 {
     for (uint32_t i = 0; i < s->slots; ++i) {
@@ -309,11 +322,11 @@ void retire(ace_stream *s, bool block)
         }
         if (q == 0) continue;
         const double t = now_s();
+        const uint8_t *res = sl.result;
         for (Request *r : sl.members) {
             if (q > 0) {
-                const uint8_t *st = s->staging + r->stage_off;
-                if (r->n) memcpy(r->h_mask, st + r->lay.off_mask, 4 * ((r->n + 31) / 32));
-                memcpy(r->h_count, st + r->lay.off_count, 8);
+                if (r->n) memcpy(r->h_mask, res + r->out_rel, 4 * ((r->n + 31) / 32));
+                memcpy(r->h_count, res + r->out_rel + r->lay.mask_bytes, 8);
                 r->status = ACE_OK;
                 s->stats.completed++;
             } else {
@@ -321,18 +334,16 @@ void retire(ace_stream *s, bool block)
                 s->stats.failed++;
             }
             r->t_done = t;
-            s->stage_alloc.release(r->stage_off, r->lay.bytes);
-            s->arena_alloc.release(r->dev_off, r->lay.bytes);
         }
-        if (sl.ws_bytes) s->arena_alloc.release(sl.ws_off, sl.ws_bytes);
-        sl.members.clear();
-        sl.ws_bytes = 0;
-        sl.busy = false;
+        release_batch(s, sl);
         s->cv_done.notify_all();
     }
 }
 
-// Server side: form and launch one batch on a free slot (lock held).
+// Server side: form and launch one batch on a free slot (lock held).  The
+// batch takes one arena range -- every request's inputs back to back, then
+// all outputs, then the workspace -- so requests whose staging copies are
+// adjacent go up in one copy, and all results come back in one copy.
 bool admit(ace_stream *s)
 {
     if (s->pending.empty()) return false;
@@ -345,70 +356,95 @@ bool admit(ace_stream *s)
         for (uint32_t i = 0; i < s->slots; ++i)
             if (s->slot[i].busy) return false;
 
-    auto &sl = s->slot[free_slot];
-    std::vector<Request *> batch;
-    std::vector<ace_block> blocks;
+    // candidates in arrival order, within the count and transaction caps
     const size_t limit = s->plain ? 1 : kMaxBatchRequests;
-    uint8_t *arena = s->be->arena();
-    while (!s->pending.empty() && batch.size() < limit) {
-        Request *r = s->pending.front();
-        size_t off;
-        if (!s->arena_alloc.alloc(r->lay.bytes, off)) break;
-        r->dev_off = off;  // allocator offset; the arena address adds arena_reserved
-        batch.push_back(r);
-        s->pending.pop_front();
-        uint8_t *d = arena + s->arena_reserved + r->dev_off;
-        ace_block b;
-        b.d_msg = d + r->lay.off_msg;
-        b.d_off = reinterpret_cast<const uint64_t *>(d + r->lay.off_off);
-        b.d_id = reinterpret_cast<const uint32_t *>(d + r->lay.off_id);
-        b.d_tag = d + r->lay.off_tag;
-        b.n_tx = r->n;
-        b.d_bitmask_out = reinterpret_cast<uint32_t *>(d + r->lay.off_mask);
-        b.d_count_out = reinterpret_cast<uint64_t *>(d + r->lay.off_count);
-        blocks.push_back(b);
+    size_t m = 0;
+    uint64_t tx = 0, out = 0;
+    while (m < s->pending.size() && m < limit) {
+        const Request *r = s->pending[m];
+        if (m && (tx + r->n > kMaxBatchTx || out + r->lay.out_bytes > kResultBytes)) break;
+        tx += r->n;
+        out += r->lay.out_bytes;
+        ++m;
     }
-    // workspace for the batch; give requests back until it fits
-    size_t ws_bytes = 0, ws_off = 0;
-    while (!batch.empty()) {
-        ws_bytes = s->be->ws_size(blocks.data(), (uint32_t)blocks.size());
-        if (ws_bytes && s->arena_alloc.alloc(ws_bytes, ws_off)) break;
-        Request *r = batch.back();
-        s->arena_alloc.release(r->dev_off, r->lay.bytes);
-        s->pending.push_front(r);
-        batch.pop_back();
-        blocks.pop_back();
-        ws_bytes = 0;
+    // largest prefix whose arena range (inputs, outputs, workspace) and result
+    // area fit now
+    std::vector<ace_block> blocks;
+    size_t arena_off = 0, arena_bytes = 0, in_total = 0, out_total = 0;
+    while (m > 0) {
+        in_total = out_total = 0;
+        blocks.assign(m, ace_block{});
+        for (size_t k = 0; k < m; ++k) {
+            const Request *r = s->pending[k];
+            in_total += r->lay.in_bytes;
+            out_total += r->lay.out_bytes;
+            ace_block &bk = blocks[k];
+            const uintptr_t fake = 0x1000;  // sizes only: real addresses are set below
+            bk.d_msg = reinterpret_cast<const uint8_t *>(fake);
+            bk.d_off = reinterpret_cast<const uint64_t *>(fake);
+            bk.d_id = reinterpret_cast<const uint32_t *>(fake);
+            bk.d_tag = reinterpret_cast<const uint8_t *>(fake);
+            bk.d_bitmask_out = reinterpret_cast<uint32_t *>(fake);
+            bk.d_count_out = reinterpret_cast<uint64_t *>(fake);
+            bk.n_tx = r->n;
+        }
+        const size_t ws = align_up(s->be->ws_size(blocks.data(), (uint32_t)m), 256);
+        arena_bytes = in_total + align_up(out_total, 256) + ws;
+        if (ws && s->arena_alloc.alloc(arena_bytes, arena_off)) break;
+        m = m > 1 ? m - std::max<size_t>(1, m / 4) : 0;
     }
-    if (batch.empty()) return false;
+    if (m == 0) return false;
+
+    auto &sl = s->slot[free_slot];
+    std::vector<Request *> batch(s->pending.begin(), s->pending.begin() + m);
+    s->pending.erase(s->pending.begin(), s->pending.begin() + m);
+    uint8_t *arena = s->be->arena() + s->arena_reserved;
+    uint8_t *base = arena + arena_off;
+    uint8_t *out_base = base + in_total;
+    size_t in_rel = 0, out_rel = 0;
+    std::vector<size_t> in_pos(m);
+    for (size_t k = 0; k < m; ++k) {
+        Request *r = batch[k];
+        in_pos[k] = in_rel;
+        r->out_rel = out_rel;
+        uint8_t *d = base + in_rel;
+        ace_block &bk = blocks[k];
+        bk.d_msg = d + r->lay.off_msg;
+        bk.d_off = reinterpret_cast<const uint64_t *>(d + r->lay.off_off);
+        bk.d_id = reinterpret_cast<const uint32_t *>(d + r->lay.off_id);
+        bk.d_tag = d + r->lay.off_tag;
+        bk.d_bitmask_out = reinterpret_cast<uint32_t *>(out_base + out_rel);
+        bk.d_count_out = reinterpret_cast<uint64_t *>(out_base + out_rel + r->lay.mask_bytes);
+        in_rel += r->lay.in_bytes;
+        out_rel += r->lay.out_bytes;
+    }
+    uint8_t *ws_ptr = out_base + align_up(out_total, 256);
+    const size_t ws_bytes = arena_bytes - in_total - align_up(out_total, 256);
 
     const double t = now_s();
     for (Request *r : batch) r->t_admit = t;
     sl.busy = true;
-    sl.launching = true;  // retire() leaves the slot alone until the copies and launch are queued
+    sl.launching = true;  // retire() leaves the slot alone until everything is queued
     sl.members = batch;
-    sl.ws_off = ws_off;
-    sl.ws_bytes = ws_bytes;
-    const size_t reserved = s->arena_reserved;
+    sl.arena_off = arena_off;
+    sl.arena_bytes = arena_bytes;
     uint8_t *staging = s->staging;
 
     // device calls without the lock, so submitters are never held up by them
     s->mu.unlock();
     int rc = s->be->begin_slot(free_slot);
-    for (size_t k = 0; !rc && k < batch.size(); ++k) {
-        Request *r = batch[k];
-        rc = s->be->h2d(free_slot, arena + reserved + r->dev_off, staging + r->stage_off,
-                        r->lay.in_bytes);
+    for (size_t k = 0; !rc && k < m;) {
+        // one copy per run of requests whose staging inputs are adjacent
+        size_t j = k + 1, bytes = batch[k]->lay.in_bytes;
+        while (j < m && batch[j]->stage_off == batch[j - 1]->stage_off + batch[j - 1]->lay.in_bytes) {
+            bytes += batch[j]->lay.in_bytes;
+            ++j;
+        }
+        rc = s->be->h2d(free_slot, base + in_pos[k], staging + batch[k]->stage_off, bytes);
+        k = j;
     }
-    if (!rc)
-        rc = s->be->verify(free_slot, blocks.data(), (uint32_t)blocks.size(),
-                           arena + reserved + ws_off, ws_bytes);
-    for (size_t k = 0; !rc && k < batch.size(); ++k) {
-        Request *r = batch[k];
-        rc = s->be->d2h(free_slot, staging + r->stage_off + r->lay.off_mask,
-                        arena + reserved + r->dev_off + r->lay.off_mask,
-                        r->lay.bytes - r->lay.off_mask);
-    }
+    if (!rc) rc = s->be->verify(free_slot, blocks.data(), (uint32_t)m, ws_ptr, ws_bytes);
+    if (!rc) rc = s->be->d2h(free_slot, sl.result, out_base, out_total);
     if (!rc) rc = s->be->end_slot(free_slot);
     if (rc) s->be->wait(free_slot);  // let whatever was queued drain before reusing memory
     s->mu.lock();
@@ -420,18 +456,13 @@ bool admit(ace_stream *s)
             r->status = rc;
             r->t_done = te;
             s->stats.failed++;
-            s->stage_alloc.release(r->stage_off, r->lay.bytes);
-            s->arena_alloc.release(r->dev_off, r->lay.bytes);
         }
-        s->arena_alloc.release(ws_off, ws_bytes);
-        sl.members.clear();
-        sl.ws_bytes = 0;
-        sl.busy = false;
+        release_batch(s, sl);
         s->cv_done.notify_all();
         return true;
     }
     s->stats.batches++;
-    s->stats.max_batch_requests = std::max<uint64_t>(s->stats.max_batch_requests, batch.size());
+    s->stats.max_batch_requests = std::max<uint64_t>(s->stats.max_batch_requests, m);
     return true;
 }
 
@@ -482,6 +513,17 @@ static int stream_start(ace_stream *s, size_t arena_bytes, size_t staging_bytes,
         if (!s->staging) return fail(ACE_ERR_NO_MEMORY, "staging allocation failed");
     }
     s->stage_alloc.reset(staging_bytes);
+    for (auto &sl : s->slot) {
+        if (pinned) {
+            void *h = nullptr;
+            int rc = check_hip(hipHostMalloc(&h, kResultBytes, hipHostMallocDefault), "hipHostMalloc results");
+            if (rc) return rc;
+            sl.result = static_cast<uint8_t *>(h);
+        } else {
+            sl.result = static_cast<uint8_t *>(malloc(kResultBytes));
+            if (!sl.result) return fail(ACE_ERR_NO_MEMORY, "result buffer allocation failed");
+        }
+    }
     s->server = std::thread(serve, s);
     return ACE_OK;
 }
@@ -489,6 +531,11 @@ static int stream_start(ace_stream *s, size_t arena_bytes, size_t staging_bytes,
 static void stream_free(ace_stream *s)
 {
     if (!s) return;
+    for (auto &sl : s->slot) {
+        if (!sl.result) continue;
+        if (s->staging_pinned) hipHostFree(sl.result);
+        else free(sl.result);
+    }
     if (s->staging) {
         if (s->staging_pinned) hipHostFree(s->staging);
         else free(s->staging);
@@ -590,15 +637,18 @@ ACE_API int ace_verify_stream(ace_stream *s, const uint8_t *h_msg, const uint64_
     }
     const size_t msg_bytes = (size_t)(hi - lo);
     const ReqLayout lay = ReqLayout::of(n_tx, msg_bytes);
-    const size_t dev_need = lay.bytes + align_up(s->be->ws_bound(n_tx), 256);
-    if (lay.bytes > s->stage_alloc.capacity() || dev_need > s->arena_alloc.capacity())
+    const size_t stage_need = lay.in_bytes;
+    const size_t dev_need = lay.in_bytes + align_up(lay.out_bytes, 256) +
+                            align_up(s->be->ws_bound(n_tx), 256);
+    if (stage_need > s->stage_alloc.capacity() || dev_need > s->arena_alloc.capacity() ||
+        n_tx > kMaxBatchTx)
         return fail(ACE_ERR_TOO_LARGE, "request needs %zu staging and %zu arena bytes; staging %zu, arena %zu",
-                    lay.bytes, dev_need, s->stage_alloc.capacity(), s->arena_alloc.capacity());
+                    stage_need, dev_need, s->stage_alloc.capacity(), s->arena_alloc.capacity());
 
     std::unique_lock<std::mutex> lock(s->mu);
     if (s->stop) return fail(ACE_ERR_INVALID_ARG, "stream is being destroyed");
     size_t stage_off;
-    while (!s->stage_alloc.alloc(lay.bytes, stage_off)) {
+    while (!s->stage_alloc.alloc(lay.in_bytes, stage_off)) {
         if (flags & ACE_NONBLOCK) return fail(ACE_ERR_AGAIN, "staging full");
         s->cv_done.wait(lock);
     }
