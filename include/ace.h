@@ -166,8 +166,10 @@ ACE_API int ace_set_tuning(const ace_tuning *t);
  * fixed, into two graph instances that read their block list from pinned host
  * memory through a device-side plan kernel; so one capture replays for any
  * mix of block count, block sizes and message lengths within the maxima.
- * Every grid is fixed: the verify kernel is the persistent one (binned mode)
- * or a grid-stride in-order one (flag ACE_ORDERED).
+ * Every grid is fixed: the binned verify kernel is launched for the largest
+ * batch (surplus waves exit at once) or, with ACE_PERSISTENT, as the
+ * persistent kernel; the in-order form (flag ACE_ORDERED) is a grid-stride
+ * kernel.
  *   d_workspace  at least ace_graph_workspace_size() bytes, 256-byte aligned,
  *                owned by the graph until ace_graph_destroy.
  * ace_graph_launch enqueues one replay on `stream` for the given blocks (the

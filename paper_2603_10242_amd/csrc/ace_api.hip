@@ -222,7 +222,7 @@ void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t 
     else if (flags & ACE_BUCKETED) p.mode = kBinned;
     else p.mode = total >= t.binned_min_tx ? kBinned : kOrdered;
     const bool binned = p.mode == kBinned;
-    p.persistent = binned && (graph || (flags & ACE_PERSISTENT) ||
+    p.persistent = binned && ((flags & ACE_PERSISTENT) ||
                               (!(flags & (ACE_ORDERED | ACE_BUCKETED)) && t.auto_persistent));
     p.max_pos = total + 64ull * kBins;
     const bool table = graph || n_blocks > 1;

@@ -83,13 +83,20 @@ struct HkdfPrep {
 // One transaction in bin order, written by the scatter pass so that the
 // verify kernel reads contiguous records instead of gathering offsets and
 // identities from scattered lines.
-constexpr uint32_t kRecWide = 0xFFFFFFFFu;     // len: too long for 32 bits, re-read the offsets
+constexpr uint32_t kRecWide = 0xFFFFFFFFu;     // len: 2^31 - 1 bytes or more, re-read the offsets
+constexpr uint32_t kRecNearEnd = 0x80000000u;  // len flag: the block's message area ends within
+                                               // kOverread bytes after this message
 constexpr uint32_t kRecInvalid = 0xFFFFFFFFu;  // id: the transaction cannot be valid
 struct TxRec {
     uint64_t addr;  // address of the first message byte
-    uint32_t len;   // message length, or kRecWide
+    uint32_t len;   // message length | kRecNearEnd, or kRecWide
     uint32_t id;    // identity index, or kRecInvalid
 };
+
+// Bytes past a message's end that the block loads of its last blocks may
+// read: 17 dwords from the aligned start of the last block, whose message
+// part is at least L - 64 * (nb - 1) > -9 bytes, give at most 76.
+constexpr uint64_t kOverread = 80;
 
 struct KeySource {
     const uint32_t *mid;   // [n_id][16] midstates, or NULL when keys come from rev
@@ -105,6 +112,19 @@ struct DescChunk {
     uint32_t first;
     uint32_t count;
 };
+
+// Occupancy targets (waves per SIMD) that the hash kernels reach without
+// spilling when the block computation is the looped form; the register
+// allocator is asked for them explicitly because on its own it trades
+// occupancy for scheduling freedom (about 120 VGPRs, 4 waves).
+#ifndef ACE_WAVES_HINTS
+#define ACE_WAVES_HINTS 1
+#endif
+#if ACE_WAVES_HINTS
+#define ACE_WAVES(n) __attribute__((amdgpu_waves_per_eu(n, n)))
+#else
+#define ACE_WAVES(n)
+#endif
 
 __host__ __device__ inline uint32_t bin_of_length(uint64_t L)
 {

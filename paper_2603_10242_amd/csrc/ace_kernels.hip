@@ -228,7 +228,7 @@ __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], 
 #pragma unroll
             for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
         }
-        if (live) compress(in, W);
+        if (live) compress_block(in, W);
         x = in;
     }
     // after the loop: A = k, B = F(IV, k^ipad), x = F(IV, k^opad)
@@ -241,7 +241,7 @@ __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], 
 // ------------------------------------------------------------------------------------------
 // k_derive: one identity per lane.
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
+__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
                                                 uint8_t *__restrict__ key_out,
                                                 uint32_t *__restrict__ mid_out, HkdfParams hp)
 {
@@ -286,6 +286,7 @@ struct TxRef {
     const uint32_t *mid;  // midstate row (ipad 0..7, opad 8..15), if cached
     const uint8_t *rev;   // root entropy row, if derived per transaction
     const uint8_t *tag;   // credential
+    bool overread_ok;     // reading up to kOverread bytes past the message end stays in its block
 };
 
 template <bool PER_TX_KEYS>
@@ -326,12 +327,13 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
     const uint32_t sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
     const uint64_t lim = (uint64_t)sh + L;                  // dword k holds message bytes iff 4k < lim
     const uint64_t last = lim ? ((lim - 1) >> 2) : 0;
-    // every load address is clamped to a dword that holds message bytes (or,
-    // for an empty message, to the credential): nothing outside the
-    // caller's buffers is touched, and clamped values only feed bytes the
-    // padding overwrites.
-    const uint32_t *A0 = lim ? reinterpret_cast<const uint32_t *>(addr - sh)
-                             : reinterpret_cast<const uint32_t *>(t.tag);
+    // Loads either stay within kOverread bytes past the message end inside the
+    // block's message area (overread_ok), or every address is clamped to a
+    // dword that holds message bytes (for an empty message, the credential):
+    // nothing outside the caller's buffers is touched, and bytes past the
+    // message end only feed words the padding overwrites.
+    const uint32_t *A0 = (lim || t.overread_ok) ? reinterpret_cast<const uint32_t *>(addr - sh)
+                                                : reinterpret_cast<const uint32_t *>(t.tag);
     const uint32_t len_hi = (uint32_t)((64 + L) >> 29);
     const uint32_t len_lo = (uint32_t)((64 + L) << 3);
 
@@ -346,7 +348,9 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
                 const uint64_t g0 = 16ull * b;
                 const int64_t rb = (int64_t)L - 64 * (int64_t)b;  // message bytes from this block on
                 uint32_t D[17];
-                if (rb >= 64) {
+                if (t.overread_ok || rb >= 64) {
+                    // whole 16-byte loads; past the message end they only read bytes of
+                    // the same block's message area, which the padding overwrites
                     const uint32_t *q = A0 + g0;
                     const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
                     D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
@@ -354,23 +358,30 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
                     D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
                     D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
                     const uint64_t k16 = g0 + 16;
-                    D[16] = A0[k16 < last ? k16 : last];
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+                    D[16] = t.overread_ok ? q[16] : A0[k16 < last ? k16 : last];
                 } else {
+                    // the last message before the end of its block's area: every
+                    // dword address is clamped to one that holds message bytes
 #pragma unroll
                     for (int k = 0; k < 17; ++k) {
                         const uint64_t idx = g0 + k;
                         D[k] = A0[idx < last ? idx : last];
                     }
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+                if (rb < 64) {
+                    // padding: word jf holds byte rb (the 0x80 marker) after its c
+                    // message bytes; earlier words are message, later ones zero
                     const int32_t r0 = (int32_t)rb;
+                    const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
+                    const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
+                    const uint32_t keep = ~(0xFFFFFFFFu >> c8);
+                    const uint32_t pad = 0x80000000u >> c8;
 #pragma unroll
                     for (int j = 0; j < 16; ++j) {
-                        const int32_t r = r0 - 4 * j;  // message bytes left at word j
-                        const uint32_t wf = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
-                        const uint32_t s8 = ((uint32_t)r & 3u) << 3;
-                        const uint32_t part = (wf & ~(0xFFFFFFFFu >> s8)) | (0x80000000u >> s8);
-                        W[j] = r >= 4 ? wf : (r >= 0 ? part : 0u);
+                        const uint32_t part = (W[j] & keep) | pad;
+                        W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
                     }
                     if (b + 1 == nb) {
                         W[14] = len_hi;
@@ -387,7 +398,7 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
                 for (int i = 9; i < 15; ++i) W[i] = 0u;
                 W[15] = 768u;
             }
-            compress(in, W);
+            compress_block(in, W);
             S = in;
         }
     }
@@ -418,6 +429,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
     t.mid = ks.mid ? ks.mid + 16ull * (ok ? who : 0u) : nullptr;
     t.rev = ks.rev ? ks.rev + 32ull * (ok ? who : 0u) : nullptr;
     t.tag = d.tag + 32ull * i;
+    t.overread_ok = ok && e + kOverread <= d.off[d.n];
     return ok;
 }
 
@@ -426,7 +438,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
 // one block; the ballot is that block's two bitmask words.
 // ------------------------------------------------------------------------------------------
 template <bool PER_TX_KEYS>
-__global__ void __launch_bounds__(kWG) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
+__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 6) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
 {
     __shared__ HkdfPrep prep;
     if constexpr (PER_TX_KEYS) {
@@ -529,6 +541,7 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
         const uint32_t b = find_block<0>(bt, T, tile);
         const DevBlock d = get_block(bt, T, b);
         const uint64_t i0 = (tile - d.tile0) * kTile;
+        const uint64_t area_end = d.off[d.n];  // end of the block's message area
         if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
         __syncthreads();
         uint32_t bins[kPer], rank[kPer];
@@ -543,7 +556,8 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
                 const bool ok = a <= e && who < n_id;
                 const uint64_t L = ok ? e - a : 0;
                 r[k].addr = reinterpret_cast<uint64_t>(d.msg + a);
-                r[k].len = L >= kRecWide ? kRecWide : (uint32_t)L;
+                r[k].len = L >= (kRecWide >> 1) ? kRecWide
+                                                : (uint32_t)L | (e + kOverread <= area_end ? 0u : kRecNearEnd);
                 r[k].id = ok ? who : kRecInvalid;
                 bins[k] = bin_of_length(L);
                 rank[k] = atomicAdd(&cnt[bins[k]], 1u);
@@ -572,7 +586,7 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
 // all in one bin; verdicts go to a bin-order bitmap.
 // ------------------------------------------------------------------------------------------
 template <bool PER_TX_KEYS, bool PERSISTENT>
-__global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
+__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 7) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
                                                        const TxRec *__restrict__ rec,
@@ -623,7 +637,8 @@ __global__ void __launch_bounds__(kWG) k_verify_binned(Batch bt, KeySource ks, H
                 live = r.id != kRecInvalid;
                 const uint32_t who = live ? r.id : 0u;
                 t.msg = reinterpret_cast<const uint8_t *>(r.addr);
-                t.L = r.len;
+                t.L = r.len & ~kRecNearEnd;
+                t.overread_ok = (r.len & kRecNearEnd) == 0;
                 t.mid = ks.mid ? ks.mid + 16ull * who : nullptr;
                 t.rev = ks.rev ? ks.rev + 32ull * who : nullptr;
                 t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) + 32ull * i;

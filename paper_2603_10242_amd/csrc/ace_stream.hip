@@ -258,9 +258,14 @@ double now_s()
 }
 
 constexpr uint32_t kMaxBatchRequests = 4096;
-constexpr uint64_t kMaxBatchTx = 16ull << 20;  // keeps one batch's latency bounded
+// A batch is capped so that its upload stays around a millisecond: requests
+// queued behind a running batch then join the next one instead of one huge
+// batch whose copy alone takes tens of milliseconds.
+constexpr uint64_t kMaxBatchTx = 1ull << 20;
+constexpr size_t kMaxBatchBytes = 32ull << 20;
+constexpr uint64_t kMaxRequestTx = 16ull << 20;  // one request (it may form a batch alone)
 // per-slot pinned result buffer: every request's bitmask (8-byte padded) and count
-constexpr size_t kResultBytes = kMaxBatchTx / 8 + 16ull * kMaxBatchRequests + 4096;
+constexpr size_t kResultBytes = (16ull << 20) / 8 + 16ull * kMaxBatchRequests + 4096;
 
 }  // namespace
 
@@ -359,12 +364,15 @@ bool admit(ace_stream *s)
     // candidates in arrival order, within the count and transaction caps
     const size_t limit = s->plain ? 1 : kMaxBatchRequests;
     size_t m = 0;
-    uint64_t tx = 0, out = 0;
+    uint64_t tx = 0, out = 0, in = 0;
     while (m < s->pending.size() && m < limit) {
         const Request *r = s->pending[m];
-        if (m && (tx + r->n > kMaxBatchTx || out + r->lay.out_bytes > kResultBytes)) break;
+        if (m && (tx + r->n > kMaxBatchTx || out + r->lay.out_bytes > kResultBytes ||
+                  in + r->lay.in_bytes > kMaxBatchBytes))
+            break;
         tx += r->n;
         out += r->lay.out_bytes;
+        in += r->lay.in_bytes;
         ++m;
     }
     // largest prefix whose arena range (inputs, outputs, workspace) and result
@@ -641,7 +649,7 @@ ACE_API int ace_verify_stream(ace_stream *s, const uint8_t *h_msg, const uint64_
     const size_t dev_need = lay.in_bytes + align_up(lay.out_bytes, 256) +
                             align_up(s->be->ws_bound(n_tx), 256);
     if (stage_need > s->stage_alloc.capacity() || dev_need > s->arena_alloc.capacity() ||
-        n_tx > kMaxBatchTx)
+        n_tx > kMaxRequestTx)
         return fail(ACE_ERR_TOO_LARGE, "request needs %zu staging and %zu arena bytes; staging %zu, arena %zu",
                     stage_need, dev_need, s->stage_alloc.capacity(), s->arena_alloc.capacity());
 

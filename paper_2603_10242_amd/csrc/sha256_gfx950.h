@@ -104,6 +104,72 @@ __device__ __forceinline__ void compress(State &s, uint32_t (&W)[16])
     s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
 }
 
+// The same block computation with rounds 16..63 as a three-iteration loop of
+// sixteen rounds.  Their constants come from one scalar load of sixteen words
+// per iteration; the loop boundary keeps the scheduler from interleaving all
+// 64 rounds, which roughly halves the VGPRs a lane needs (more waves per SIMD)
+// at the same 1,384 VALU instructions per block.
+__constant__ __attribute__((aligned(64))) uint32_t kRoundTable[64] = {
+    0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,
+    0xab1c5ed5u, 0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu,
+    0x9bdc06a7u, 0xc19bf174u, 0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu,
+    0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau, 0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u,
+    0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u, 0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu,
+    0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u, 0xa2bfe8a1u, 0xa81a664bu,
+    0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u, 0x19a4c116u,
+    0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
+    0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u,
+    0xc67178f2u};
+
+struct RoundConsts16 {
+    uint32_t k[16];
+};
+
+__device__ __forceinline__ void round_step(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d,
+                                           uint32_t &e, uint32_t &f, uint32_t &g, uint32_t &h,
+                                           uint32_t wt, uint32_t kt)
+{
+    const uint32_t t1 = (h + wt + kt) + (big_sigma1(e) + ch(e, f, g));
+    const uint32_t t2 = big_sigma0(a) + maj(a, b, c);
+    h = g; g = f; f = e; e = d + t1;
+    d = c; c = b; b = a; a = t1 + t2;
+}
+
+__device__ __forceinline__ void compress_looped(State &s, uint32_t (&W)[16])
+{
+    uint32_t a = s.h[0], b = s.h[1], c = s.h[2], d = s.h[3];
+    uint32_t e = s.h[4], f = s.h[5], g = s.h[6], h = s.h[7];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) round_step(a, b, c, d, e, f, g, h, W[j], kRound[j]);
+#pragma nounroll
+    for (int q = 1; q < 4; ++q) {
+        const RoundConsts16 kq = *reinterpret_cast<const RoundConsts16 *>(&kRoundTable[16 * q]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t wt = small_sigma1(W[(j - 2) & 15]) + W[(j - 7) & 15] +
+                                small_sigma0(W[(j - 15) & 15]) + W[j];
+            W[j] = wt;
+            round_step(a, b, c, d, e, f, g, h, wt, kq.k[j]);
+        }
+    }
+    s.h[0] += a; s.h[1] += b; s.h[2] += c; s.h[3] += d;
+    s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
+}
+
+#ifndef ACE_COMPRESS_LOOPED
+#define ACE_COMPRESS_LOOPED 1
+#endif
+
+// The block computation the kernels use.
+__device__ __forceinline__ void compress_block(State &s, uint32_t (&W)[16])
+{
+#if ACE_COMPRESS_LOOPED
+    compress_looped(s, W);
+#else
+    compress(s, W);
+#endif
+}
+
 // Compression of a block whose words 8..15 are the fixed tail of a 32-byte
 // message after a 64-byte key block: 0x80 marker, zeros, bit length
 // (64 + 32) * 8 = 768.  Used for HMAC outer hashes and for 32-byte inputs.
