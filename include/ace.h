@@ -118,7 +118,8 @@ typedef struct {
     size_t info_len;
 } ace_keyset;
 
-/* Workspace bytes ace_verify_batch needs for these arguments (0 on bad arguments). */
+/* Workspace bytes ace_verify_batch (or ace_verify_attestations) needs for these
+ * arguments (0 on bad arguments). */
 ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,
                                          uint32_t n_blocks, uint32_t flags);
 
@@ -137,6 +138,25 @@ ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block
  */
 ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
                              void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * ace_verify_attestations -- the paper's attestation form (Def. 3.1 with the
+ * validator's payload binding of Alg. 2), over n_blocks blocks in one pass.
+ * Each transaction carries a payload P and a 72-byte attestation record
+ *   obj_hash (32 bytes) || domain (8 bytes, opaque) || credential (32 bytes)
+ * and
+ *   valid_i = (id_i < n_id) and (off_i <= off_{i+1}) and
+ *             SHA-256(P_i) == obj_hash_i and
+ *             HMAC-SHA256(k_{id_i}, obj_hash_i || domain_i) == credential_i
+ * (both compares over all 32 bytes, no early exit).  The ace_block fields
+ * are read as: d_msg / d_off the payloads, d_tag [n_tx][72] the attestation
+ * records (4-byte aligned); the rest as in ace_verify_batch.  Keyset, flags,
+ * workspace (ace_verify_workspace_size with the same arguments), errors and
+ * stream semantics are those of ace_verify_batch.
+ */
+ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blocks,
+                                    uint32_t n_blocks, void *d_workspace, size_t ws_bytes,
+                                    uint32_t flags, void *stream);
 
 /*
  * Tuning of the launch shapes (process-wide).  The autotuner measures the

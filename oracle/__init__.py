@@ -16,4 +16,5 @@ from .oracle import (  # noqa: F401
     derive_keys,
     verify_batch,
     verify_batch_rev,
+    verify_attest,
 )

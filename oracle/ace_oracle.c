@@ -249,6 +249,8 @@ typedef struct {
     const uint8_t *keys; uint32_t n_id;
     const uint8_t *msg; const uint64_t *off; const uint32_t *id; const uint8_t *tag;
     uint32_t *bitmask; uint64_t count;
+    /* paper-form attestation */
+    const uint8_t *att; /* [n][72]: obj_hash (32) || domain (8) || credential (32) */
 } job_t;
 
 /* Full 32-byte compare with no early exit: OR of the XORs of all bytes. */
@@ -273,7 +275,17 @@ static void *run_job(void *arg)
         int valid = 0;
         uint32_t who = j->id[i];
         uint64_t a = j->off[i], b = j->off[i + 1];
-        if (who < j->n_id && a <= b) {
+        if (j->kind == 2) {
+            /* Def. 3.1 / Alg. 2: obj_hash = SHA-256(P) (payload binding) and
+             * credential = HMAC(k, obj_hash || domain), identity registered. */
+            if (who < j->n_id && a <= b) {
+                const uint8_t *A = j->att + 72 * i;
+                uint8_t h[32], mac[32];
+                oracle_sha256(j->msg + a, (size_t)(b - a), h);
+                oracle_hmac_sha256(j->keys + 32 * (size_t)who, 32, A, 40, mac);
+                valid = cteq32(h, A) & cteq32(mac, A + 40);
+            }
+        } else if (who < j->n_id && a <= b) {
             uint8_t mac[32];
             oracle_hmac_sha256(j->keys + 32 * (size_t)who, 32, j->msg + a, (size_t)(b - a), mac);
             valid = cteq32(mac, j->tag + 32 * i);
@@ -340,6 +352,24 @@ void oracle_verify_batch(const uint8_t *keys, uint32_t n_id, const uint8_t *msg,
     memset(&t, 0, sizeof t);
     t.kind = 1;
     t.keys = keys; t.n_id = n_id; t.msg = msg; t.off = off; t.id = id; t.tag = tag;
+    t.bitmask = bitmask_out;
+    run_split(&t, (size_t)n, nthreads, 32, count_out);
+}
+
+/* Paper-form attestation check of Def. 3.1 and Alg. 2 (the "full check"):
+ *   valid_i = (id_i < n_id) and (poff_i <= poff_{i+1})
+ *             and SHA-256(payload_i) == obj_hash_i
+ *             and HMAC-SHA256(k_{id_i}, obj_hash_i || domain_i) == credential_i
+ * with att_i = obj_hash (32) || domain (8) || credential (32). */
+void oracle_verify_attest(const uint8_t *keys, uint32_t n_id, const uint8_t *payload,
+                          const uint64_t *poff, const uint32_t *id, const uint8_t *att, uint64_t n,
+                          uint32_t *bitmask_out, uint64_t *count_out, int nthreads)
+{
+    memset(bitmask_out, 0, sizeof(uint32_t) * (size_t)((n + 31) / 32));
+    job_t t;
+    memset(&t, 0, sizeof t);
+    t.kind = 2;
+    t.keys = keys; t.n_id = n_id; t.msg = payload; t.off = poff; t.id = id; t.att = att;
     t.bitmask = bitmask_out;
     run_split(&t, (size_t)n, nthreads, 32, count_out);
 }

@@ -53,6 +53,8 @@ def _load():
                                        ctypes.c_int]
     lib.oracle_verify_batch.argtypes = [_u8p, ctypes.c_uint32, _u8p, _u64p, _u32p, _u8p,
                                         ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
+    lib.oracle_verify_attest.argtypes = [_u8p, ctypes.c_uint32, _u8p, _u64p, _u32p, _u8p,
+                                         ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -155,3 +157,23 @@ def verify_batch_rev(rev: np.ndarray, salt: bytes, info: bytes, msg, off, ids, t
     """Keys derived from REV by HKDF first (Alg. 1 Phase 1a), then verified."""
     keys = derive_keys(rev, salt, info, nthreads)
     return verify_batch(keys, msg, off, ids, tags, nthreads)
+
+
+def verify_attest(keys: np.ndarray, payload: np.ndarray, poff: np.ndarray, ids: np.ndarray,
+                  att: np.ndarray, nthreads: int = 1) -> tuple[np.ndarray, int]:
+    """Paper-form check: SHA-256(payload) == obj_hash and HMAC(k, obj_hash || domain) == cred."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+    payload = np.ascontiguousarray(payload, dtype=np.uint8)
+    poff = np.ascontiguousarray(poff, dtype=np.uint64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    att = np.ascontiguousarray(att, dtype=np.uint8).reshape(-1, 72)
+    n = ids.shape[0]
+    assert poff.shape[0] == n + 1 and att.shape[0] == n
+    mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
+    cnt = ctypes.c_uint64(0)
+    p_arg = payload if payload.size else np.zeros(1, np.uint8)
+    _load().oracle_verify_attest(_ptr(keys, _u8p) if keys.size else None, keys.shape[0],
+                                 _ptr(p_arg, _u8p), _ptr(poff, _u64p), _ptr(ids, _u32p),
+                                 _ptr(att, _u8p) if att.size else None, n, _ptr(mask, _u32p),
+                                 ctypes.byref(cnt), nthreads)
+    return mask[: (n + 31) // 32], int(cnt.value)

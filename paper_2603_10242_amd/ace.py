@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH):
     lib.ace_verify_batch.argtypes = [ctypes.POINTER(ace_keyset), ctypes.POINTER(ace_block), u32,
                                      vp, sz, u32, vp]
     lib.ace_verify_batch.restype = ctypes.c_int
+    lib.ace_verify_attestations.argtypes = lib.ace_verify_batch.argtypes
+    lib.ace_verify_attestations.restype = ctypes.c_int
     lib.ace_get_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
     lib.ace_set_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
     lib.ace_graph_workspace_size.argtypes = [ctypes.POINTER(ace_keyset), u32, ctypes.c_uint64, u32]
@@ -174,9 +176,13 @@ def to_device(a: np.ndarray, dtype=None, device="cuda") -> torch.Tensor:
     return t.to(device) if dtype is None else t.to(device=device, dtype=dtype)
 
 
-def upload_block(msg, off, ids, tags, device="cuda", msg_dev: Optional[torch.Tensor] = None
-                 ) -> DeviceBlock:
-    """Copies one block's arrays to the device and allocates its outputs."""
+def upload_block(msg, off, ids, tags, device="cuda", msg_dev: Optional[torch.Tensor] = None,
+                 record_bytes: int = 32) -> DeviceBlock:
+    """Copies one block's arrays to the device and allocates its outputs.
+
+    ``tags`` holds one check record per transaction: the 32-byte credential,
+    or (record_bytes=72) the attestation obj_hash || domain || credential.
+    """
     n = int(np.asarray(ids).shape[0])
     if msg_dev is not None:
         m = msg_dev
@@ -186,7 +192,8 @@ def upload_block(msg, off, ids, tags, device="cuda", msg_dev: Optional[torch.Ten
         m = to_device(host if host.size else np.zeros(4, np.uint8), device=device)
     return DeviceBlock(m, to_device(np.asarray(off, np.uint64), device=device),
                        to_device(np.asarray(ids, np.uint32), device=device),
-                       to_device(np.asarray(tags, np.uint8).reshape(-1, 32), device=device),
+                       to_device(np.asarray(tags, np.uint8).reshape(-1, record_bytes),
+                                 device=device),
                        torch.zeros((n + 31) // 32, dtype=torch.int32, device=device),
                        torch.zeros(1, dtype=torch.int64, device=device), n)
 
@@ -220,20 +227,31 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
-def verify_batch(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
-                 ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
-    """ace_verify_batch over the given blocks; returns the workspace used."""
+def _verify(fn, keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
+            ws: Optional[torch.Tensor], flags: int, stream) -> torch.Tensor:
     ks, keep = keyset.struct()
     arr = _blocks_array(blocks)
     lib = load()
     need = int(lib.ace_verify_workspace_size(ctypes.byref(ks), arr, len(blocks), flags))
     if need == 0 and len(blocks):
-        _check(lib.ace_verify_batch(ctypes.byref(ks), arr, len(blocks), None, 0, flags, None))
+        _check(fn(ctypes.byref(ks), arr, len(blocks), None, 0, flags, None))
     if ws is None or ws.numel() < need:
         ws = workspace(need, device=blocks[0].bitmask.device if blocks else "cuda")
-    _check(lib.ace_verify_batch(ctypes.byref(ks), arr, len(blocks), _ptr(ws), ws.numel(), flags,
-                                _stream(stream)))
+    _check(fn(ctypes.byref(ks), arr, len(blocks), _ptr(ws), ws.numel(), flags, _stream(stream)))
     return ws
+
+
+def verify_batch(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
+                 ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """ace_verify_batch over the given blocks; returns the workspace used."""
+    return _verify(load().ace_verify_batch, keyset, blocks, ws, flags, stream)
+
+
+def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
+                        ws: Optional[torch.Tensor] = None, flags: int = 0,
+                        stream=None) -> torch.Tensor:
+    """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
+    return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream)
 
 
 def midstate_keyset(rev: torch.Tensor, salt: bytes, info: bytes, stream=None) -> DeviceKeyset:

@@ -17,7 +17,7 @@
 #include <string.h>
 
 typedef struct {
-    int kind; /* 0 = keys, 1 = tags */
+    int kind; /* 0 = keys, 1 = tags, 2 = digests */
     uint64_t lo, hi;
     const uint8_t *rev, *salt, *info;
     size_t slen, ilen;
@@ -72,10 +72,25 @@ static void sign_range(job_t *j)
     EVP_MAC_free(mac);
 }
 
+static void digest_range(job_t *j)
+{
+    for (uint64_t i = j->lo; i < j->hi; ++i) {
+        unsigned int outl = 0;
+        const uint8_t *m = j->msg + j->off[i];
+        size_t len = (size_t)(j->off[i + 1] - j->off[i]);
+        if (EVP_Digest(m, len, j->tags_out + 32 * i, &outl, EVP_sha256(), NULL) <= 0 || outl != 32) {
+            j->status = -2;
+            break;
+        }
+    }
+}
+
 static void *run(void *arg)
 {
     job_t *j = (job_t *)arg;
-    if (j->kind == 0) derive_range(j); else sign_range(j);
+    if (j->kind == 0) derive_range(j);
+    else if (j->kind == 1) sign_range(j);
+    else digest_range(j);
     return NULL;
 }
 
@@ -126,5 +141,15 @@ int client_sign(const uint8_t *keys, const uint8_t *msg, const uint64_t *off,
     memset(&t, 0, sizeof t);
     t.kind = 1;
     t.keys = keys; t.msg = msg; t.off = off; t.key_index = key_index; t.tags_out = tags_out;
+    return split(&t, n, nthreads);
+}
+
+/* out[i] = SHA-256(msg[off[i] .. off[i+1])) via OpenSSL. */
+int client_digest(const uint8_t *msg, const uint64_t *off, uint64_t n, uint8_t *out, int nthreads)
+{
+    job_t t;
+    memset(&t, 0, sizeof t);
+    t.kind = 2;
+    t.msg = msg; t.off = off; t.tags_out = out;
     return split(&t, n, nthreads);
 }

@@ -144,6 +144,7 @@ struct Plan {
     bool per_tx;
     bool persistent;
     bool rev;
+    bool attest;  // paper-form records (payload binding + credential over obj_hash || domain)
     uint32_t n_blocks;
     uint64_t total_tx;
     uint64_t total_tiles;
@@ -239,10 +240,11 @@ void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t 
 }
 
 int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks, uint32_t flags,
-              Plan &p)
+              Plan &p, bool attest = false)
 {
     int rc = check_keyset(keys, flags, p);
     if (rc) return rc;
+    p.attest = attest;
     uint64_t total, tiles, waves;
     if ((rc = check_blocks(blocks, n_blocks, total, tiles, waves))) return rc;
     p.total_tx = total;
@@ -272,6 +274,50 @@ DevBlock dev_block(const ace_block &k)
     d.count = reinterpret_cast<unsigned long long *>(k.d_count_out);
     d.n = k.n_tx;
     return d;
+}
+
+// Verify-kernel launches for the plan's key source, persistence and record form.
+template <bool PT, bool AT>
+void launch_ordered_t(unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
+                      const HkdfParams &hp)
+{
+    hipLaunchKernelGGL((k_verify_ordered<PT, AT>), dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+}
+
+void launch_ordered(const Plan &p, unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
+                    const HkdfParams &hp)
+{
+    if (p.attest) {
+        if (p.per_tx) launch_ordered_t<true, true>(g, s, bt, ks, hp);
+        else launch_ordered_t<false, true>(g, s, bt, ks, hp);
+    } else {
+        if (p.per_tx) launch_ordered_t<true, false>(g, s, bt, ks, hp);
+        else launch_ordered_t<false, false>(g, s, bt, ks, hp);
+    }
+}
+
+template <bool PT, bool PE, bool AT>
+void launch_binned_t(unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
+                     const HkdfParams &hp, Ctrl *ctrl, const unsigned long long *perm,
+                     const TxRec *rec, uint32_t *vperm)
+{
+    hipLaunchKernelGGL((k_verify_binned<PT, PE, AT>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl,
+                       perm, rec, vperm);
+}
+
+void launch_binned(const Plan &p, unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
+                   const HkdfParams &hp, Ctrl *ctrl, const unsigned long long *perm,
+                   const TxRec *rec, uint32_t *vperm)
+{
+#define ACE_B(PT, PE, AT) launch_binned_t<PT, PE, AT>(g, s, bt, ks, hp, ctrl, perm, rec, vperm)
+    if (p.attest) {
+        if (p.per_tx) { if (p.persistent) ACE_B(true, true, true); else ACE_B(true, false, true); }
+        else { if (p.persistent) ACE_B(false, true, true); else ACE_B(false, false, true); }
+    } else {
+        if (p.per_tx) { if (p.persistent) ACE_B(true, true, false); else ACE_B(true, false, false); }
+        else { if (p.persistent) ACE_B(false, true, false); else ACE_B(false, false, false); }
+    }
+#undef ACE_B
 }
 
 // The launch sequence after the block table is in place.  `graph` marks a
@@ -316,10 +362,7 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
         if (graph || p.total_tx) {
             const unsigned g = graph ? tn.verify_wgs_per_cu * cus
                                      : grid_for(p.total_waves, kWavesPerWG, 0x7fffffffu);
-            if (p.per_tx)
-                hipLaunchKernelGGL(k_verify_ordered<true>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
-            else
-                hipLaunchKernelGGL(k_verify_ordered<false>, dim3(g), dim3(kWG), 0, s, bt, ks, hp);
+            launch_ordered(p, g, s, bt, ks, hp);
             if ((rc = launch_status("k_verify_ordered launch"))) return rc;
         }
         prof_mark(prof, 3, s);
@@ -347,18 +390,10 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     if ((rc = launch_status("k_bin_scatter launch"))) return rc;
     prof_mark(prof, 2, s);
 
-    if (p.persistent) {
-        const unsigned g = tn.verify_wgs_per_cu * cus;
-        if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
-        else
-            hipLaunchKernelGGL((k_verify_binned<false, true>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
-    } else {
-        const unsigned g = grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
-        if (p.per_tx)
-            hipLaunchKernelGGL((k_verify_binned<true, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
-        else
-            hipLaunchKernelGGL((k_verify_binned<false, false>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl, perm, rec, vperm);
+    {
+        const unsigned g = p.persistent ? tn.verify_wgs_per_cu * cus
+                                        : grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
+        launch_binned(p, g, s, bt, ks, hp, ctrl, perm, rec, vperm);
     }
     if ((rc = launch_status("k_verify_binned launch"))) return rc;
     prof_mark(prof, 3, s);
@@ -460,12 +495,16 @@ ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block
     return p.bytes;
 }
 
-ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
-                             void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream)
+}  // extern "C"
+
+namespace {
+
+int verify_impl(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+                void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream, bool attest)
 {
     clear_error();
     Plan p;
-    int rc = make_plan(keys, blocks, n_blocks, flags, p);
+    int rc = make_plan(keys, blocks, n_blocks, flags, p, attest);
     if (rc) return rc;
     if (n_blocks == 0) return ACE_OK;
     if (!d_workspace) return fail(ACE_ERR_INVALID_ARG, "d_workspace is NULL");
@@ -513,6 +552,23 @@ ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, ui
     }
     bt.table = n_blocks > 1 ? table : nullptr;
     return enqueue_stages(p, bt, keys, hp, ws, s, prof, false);
+}
+
+}  // namespace
+
+extern "C" {
+
+ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+                             void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream)
+{
+    return verify_impl(keys, blocks, n_blocks, d_workspace, ws_bytes, flags, stream, false);
+}
+
+ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blocks,
+                                    uint32_t n_blocks, void *d_workspace, size_t ws_bytes,
+                                    uint32_t flags, void *stream)
+{
+    return verify_impl(keys, blocks, n_blocks, d_workspace, ws_bytes, flags, stream, true);
 }
 
 ACE_API int ace_profile_enable(int on)

@@ -289,12 +289,21 @@ struct TxRef {
     bool overread_ok;     // reading up to kOverread bytes past the message end stays in its block
 };
 
-template <bool PER_TX_KEYS>
+// Bytes of a transaction's check record: its credential (HMAC form), or its
+// attestation obj_hash (32) || domain (8) || credential (32) (paper form of
+// Def. 3.1, with the payload as the message).
+template <bool ATTEST>
+constexpr uint32_t check_stride() { return ATTEST ? 72u : 32u; }
+
+// HMAC form: valid iff HMAC(k, msg) == credential.
+// Paper form (ATTEST): the message is the payload P; valid iff SHA-256(P) ==
+// obj_hash (payload binding) and HMAC(k, obj_hash || domain) == credential.
+template <bool PER_TX_KEYS, bool ATTEST>
 __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const HkdfPrep *prep)
 {
-    State S, opad;
+    State S, ipad, opad;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { S.h[i] = 0; opad.h[i] = 0; }
+    for (int i = 0; i < 8; ++i) { S.h[i] = 0; ipad.h[i] = 0; opad.h[i] = 0; }
     if constexpr (PER_TX_KEYS) {
         uint32_t rv[8];
         if (live) {
@@ -307,21 +316,26 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
             for (int i = 0; i < 8; ++i) rv[i] = 0;
         }
         uint32_t key[8];
-        derive_lane(live, rv, *prep, key, S, opad);
+        derive_lane(live, rv, *prep, key, ipad, opad);
     } else {
         if (live) {
             // both halves of the 64-byte row at once: one cache line, fetched once
             const U4 a = load16(t.mid), b = load16(t.mid + 4);
             const U4 c = load16(t.mid + 8), e = load16(t.mid + 12);
-            S.h[0] = a.x; S.h[1] = a.y; S.h[2] = a.z; S.h[3] = a.w;
-            S.h[4] = b.x; S.h[5] = b.y; S.h[6] = b.z; S.h[7] = b.w;
+            ipad.h[0] = a.x; ipad.h[1] = a.y; ipad.h[2] = a.z; ipad.h[3] = a.w;
+            ipad.h[4] = b.x; ipad.h[5] = b.y; ipad.h[6] = b.z; ipad.h[7] = b.w;
             opad.h[0] = c.x; opad.h[1] = c.y; opad.h[2] = c.z; opad.h[3] = c.w;
             opad.h[4] = e.x; opad.h[5] = e.y; opad.h[6] = e.z; opad.h[7] = e.w;
         }
     }
+    // the message chain starts from the ipad state (HMAC inner hash) or, for
+    // the payload digest, from the initial value
+    if constexpr (ATTEST) S = initial_state();
+    else S = ipad;
 
     const uint64_t L = t.L;
-    const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;  // inner blocks
+    const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;  // message blocks
+    const uint32_t last_step = ATTEST ? nb + 1 : nb;                // + HMAC inner (paper form) + outer
     const uintptr_t addr = reinterpret_cast<uintptr_t>(t.msg);
     const uint32_t sh = (uint32_t)addr & 3u;
     const uint32_t sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
@@ -329,16 +343,19 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
     const uint64_t last = lim ? ((lim - 1) >> 2) : 0;
     // Loads either stay within kOverread bytes past the message end inside the
     // block's message area (overread_ok), or every address is clamped to a
-    // dword that holds message bytes (for an empty message, the credential):
-    // nothing outside the caller's buffers is touched, and bytes past the
-    // message end only feed words the padding overwrites.
+    // dword that holds message bytes (for an empty message, the check
+    // record): nothing outside the caller's buffers is touched, and bytes past
+    // the message end only feed words the padding overwrites.
     const uint32_t *A0 = (lim || t.overread_ok) ? reinterpret_cast<const uint32_t *>(addr - sh)
                                                 : reinterpret_cast<const uint32_t *>(t.tag);
-    const uint32_t len_hi = (uint32_t)((64 + L) >> 29);
-    const uint32_t len_lo = (uint32_t)((64 + L) << 3);
+    // bit length: the HMAC inner hash counts the 64-byte key block before the message
+    const uint64_t bits = ((ATTEST ? 0 : 64) + L) << 3;
+    const uint32_t len_hi = (uint32_t)(bits >> 32);
+    const uint32_t len_lo = (uint32_t)bits;
+    uint32_t bind = 0;  // paper form: OR of SHA-256(P) ^ obj_hash
 
     for (uint32_t b = 0;; ++b) {
-        const bool run = live && b <= nb;
+        const bool run = live && b <= last_step;
         if (__ballot(run) == 0) break;
         if (run) {
             uint32_t W[16];
@@ -388,6 +405,23 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
                         W[15] = len_lo;
                     }
                 }
+            } else if (ATTEST && b == nb) {
+                // S = SHA-256(P): compare with obj_hash, then the HMAC inner block
+                // over obj_hash || domain (40 bytes, bit length (64 + 40) * 8)
+                const uint32_t *ap = reinterpret_cast<const uint32_t *>(t.tag);
+                const U4 a0 = load16(ap), a1 = load16(ap + 4);
+                const uint32_t d0 = ap[8], d1 = ap[9];
+                W[0] = bswap32(a0.x); W[1] = bswap32(a0.y); W[2] = bswap32(a0.z); W[3] = bswap32(a0.w);
+                W[4] = bswap32(a1.x); W[5] = bswap32(a1.y); W[6] = bswap32(a1.z); W[7] = bswap32(a1.w);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bind = or_xor(bind, S.h[i], W[i]);
+                W[8] = bswap32(d0);
+                W[9] = bswap32(d1);
+                W[10] = 0x80000000u;
+#pragma unroll
+                for (int i = 11; i < 15; ++i) W[i] = 0u;
+                W[15] = (64u + 40u) * 8u;
+                in = ipad;
             } else {
                 // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
                 in = opad;
@@ -405,9 +439,9 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
 
     bool ok = false;
     if (live) {
-        const uint32_t *tp = reinterpret_cast<const uint32_t *>(t.tag);
+        const uint32_t *tp = reinterpret_cast<const uint32_t *>(t.tag) + (ATTEST ? 10 : 0);
         const U4 a = load16(tp), c = load16(tp + 4);
-        uint32_t d = 0;
+        uint32_t d = bind;
         d = or_xor(d, S.h[0], bswap32(a.x)); d = or_xor(d, S.h[1], bswap32(a.y));
         d = or_xor(d, S.h[2], bswap32(a.z)); d = or_xor(d, S.h[3], bswap32(a.w));
         d = or_xor(d, S.h[4], bswap32(c.x)); d = or_xor(d, S.h[5], bswap32(c.y));
@@ -419,6 +453,7 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
 
 // Loads what one lane needs about transaction i of block d.  Returns whether
 // the transaction can be valid at all (registered identity, ordered offsets).
+template <bool ATTEST>
 __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const KeySource &ks, TxRef &t)
 {
     const uint64_t a = d.off[i], e = d.off[i + 1];
@@ -428,7 +463,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
     t.L = ok ? e - a : 0;
     t.mid = ks.mid ? ks.mid + 16ull * (ok ? who : 0u) : nullptr;
     t.rev = ks.rev ? ks.rev + 32ull * (ok ? who : 0u) : nullptr;
-    t.tag = d.tag + 32ull * i;
+    t.tag = d.tag + (uint64_t)check_stride<ATTEST>() * i;
     t.overread_ok = ok && e + kOverread <= d.off[d.n];
     return ok;
 }
@@ -437,7 +472,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
 // k_verify, in-order form: wave tile w covers transactions 64w' .. 64w'+63 of
 // one block; the ballot is that block's two bitmask words.
 // ------------------------------------------------------------------------------------------
-template <bool PER_TX_KEYS>
+template <bool PER_TX_KEYS, bool ATTEST>
 __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 6) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
 {
     __shared__ HkdfPrep prep;
@@ -457,8 +492,8 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 6) k_verify_o
         const bool active = i < d.n;
         TxRef t{};
         bool live = false;
-        if (active) live = load_tx(d, i, ks, t);
-        const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
+        if (active) live = load_tx<ATTEST>(d, i, ks, t);
+        const bool valid = verify_lane<PER_TX_KEYS, ATTEST>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
         if (lane_id() == 0) {
             d.bitmask[i0 >> 5] = (uint32_t)m;
@@ -585,8 +620,8 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
 // k_verify, binned form: wave tile w covers bin-order positions 64w..64w+63,
 // all in one bin; verdicts go to a bin-order bitmap.
 // ------------------------------------------------------------------------------------------
-template <bool PER_TX_KEYS, bool PERSISTENT>
-__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 7) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
+template <bool PER_TX_KEYS, bool PERSISTENT, bool ATTEST>
+__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST && PERSISTENT ? 6 : 7)) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
                                                        const TxRec *__restrict__ rec,
@@ -632,7 +667,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 7) k_verify_b
             const uint32_t b = (uint32_t)(e >> 40);
             const uint64_t i = e & ((1ull << 40) - 1);
             if (r.len == kRecWide) {
-                live = load_tx(get_block(bt, T, b), i, ks, t);  // message of 4 GiB or more
+                live = load_tx<ATTEST>(get_block(bt, T, b), i, ks, t);  // message of 2 GiB or more
             } else {
                 live = r.id != kRecInvalid;
                 const uint32_t who = live ? r.id : 0u;
@@ -641,10 +676,11 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 7) k_verify_b
                 t.overread_ok = (r.len & kRecNearEnd) == 0;
                 t.mid = ks.mid ? ks.mid + 16ull * who : nullptr;
                 t.rev = ks.rev ? ks.rev + 32ull * who : nullptr;
-                t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) + 32ull * i;
+                t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) +
+                        (uint64_t)check_stride<ATTEST>() * i;
             }
         }
-        const bool valid = verify_lane<PER_TX_KEYS>(live, t, &prep) && live;
+        const bool valid = verify_lane<PER_TX_KEYS, ATTEST>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
         if (lane == 0) {
             vperm[2 * w] = (uint32_t)m;
@@ -767,19 +803,19 @@ __global__ void k_put_descs(DevBlock *table, DescChunk c)
 }
 
 // Explicit instantiations used by the host entry points.
-template __global__ void k_verify_ordered<false>(Batch, KeySource, HkdfParams);
-template __global__ void k_verify_ordered<true>(Batch, KeySource, HkdfParams);
-template __global__ void k_verify_binned<false, false>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                       const unsigned long long *, const TxRec *,
-                                                       uint32_t *);
-template __global__ void k_verify_binned<false, true>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                      const unsigned long long *, const TxRec *,
+template __global__ void k_verify_ordered<false, false>(Batch, KeySource, HkdfParams);
+template __global__ void k_verify_ordered<true, false>(Batch, KeySource, HkdfParams);
+template __global__ void k_verify_ordered<false, true>(Batch, KeySource, HkdfParams);
+#define ACE_BINNED(P, Q, R)                                                                     \
+    template __global__ void k_verify_binned<P, Q, R>(Batch, KeySource, HkdfParams, Ctrl *,   \
+                                                      const unsigned long long *, const TxRec *, \
                                                       uint32_t *);
-template __global__ void k_verify_binned<true, false>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                      const unsigned long long *, const TxRec *,
-                                                      uint32_t *);
-template __global__ void k_verify_binned<true, true>(Batch, KeySource, HkdfParams, Ctrl *,
-                                                     const unsigned long long *, const TxRec *,
-                                                     uint32_t *);
+ACE_BINNED(false, false, false)
+ACE_BINNED(false, true, false)
+ACE_BINNED(true, false, false)
+ACE_BINNED(true, true, false)
+ACE_BINNED(false, false, true)
+ACE_BINNED(false, true, true)
+#undef ACE_BINNED
 
 }  // namespace ace

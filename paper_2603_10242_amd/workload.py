@@ -52,6 +52,7 @@ def _lib():
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         lib.client_derive_keys.argtypes = [vp, ctypes.c_uint64, vp, sz, vp, sz, vp, ctypes.c_int]
         lib.client_sign.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
+        lib.client_digest.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
         _client = lib
     return _client
 
@@ -91,6 +92,21 @@ def client_sign(keys: np.ndarray, msg: np.ndarray, off: np.ndarray, key_index: n
     if rc != 0:
         raise RuntimeError("OpenSSL HMAC failed (%d)" % rc)
     return tags
+
+
+def client_digest(msg: np.ndarray, off: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """Client-side SHA-256 of every message (OpenSSL)."""
+    n = off.shape[0] - 1
+    out = np.zeros((n, 32), np.uint8)
+    if n == 0:
+        return out
+    msg_arg = msg if msg.size else np.zeros(1, np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    rc = _lib().client_digest(msg_arg.ctypes.data, off.ctypes.data, n, out.ctypes.data,
+                              nthreads or host_threads())
+    if rc != 0:
+        raise RuntimeError("OpenSSL SHA-256 failed (%d)" % rc)
+    return out
 
 
 @dataclasses.dataclass
@@ -293,3 +309,101 @@ def subset(w: Workload, lo: int, hi: int, name: str | None = None) -> Workload:
     return Workload(name or "%s[%d:%d]" % (w.name, lo, hi), w.rev, w.salt, w.info,
                     w.msg[a:b].copy(), off, w.ids[lo:hi].copy(), w.tags[lo:hi].copy(),
                     w.truth[lo:hi].copy(), w.keys, None, dict(w.meta))
+
+
+# ----------------------------------------------------------------------------------------
+# Paper-form attestations (Def. 3.1): payload P, obj_hash = SHA-256(P), domain = c || s
+# (8 bytes), key HKDF(REV, "ACEGF-V1-MEMPOOL-ATTEST", salt = domain), credential
+# HMAC(k, obj_hash || domain).
+# ----------------------------------------------------------------------------------------
+P_PAYLOAD, P_OBJHASH, P_DOMAIN, P_CRED, P_KEY = 0, 1, 2, 3, 4
+
+
+@dataclasses.dataclass
+class AttestWorkload:
+    name: str
+    rev: np.ndarray       # [n_id][32]
+    domain: bytes         # 8 bytes, the block's chain || slot; the HKDF salt
+    info: bytes
+    payload: np.ndarray   # u8, payloads back to back
+    poff: np.ndarray      # u64 [n+1]
+    ids: np.ndarray       # u32 [n]
+    att: np.ndarray       # u8 [n][72]: obj_hash || domain || credential
+    truth: np.ndarray
+    keys: np.ndarray
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.ids.shape[0])
+
+    @property
+    def n_id(self) -> int:
+        return int(self.rev.shape[0])
+
+    def lengths(self) -> np.ndarray:
+        return (self.poff[1:] - self.poff[:-1]).astype(np.int64)
+
+    def truth_bitmask(self) -> np.ndarray:
+        return pack_bits(self.truth)
+
+
+def paper_attestations(n: int = 2000, n_id: int = 1 << 16, seed: int = SEED_BASE + 6,
+                       lengths=None, id_dist: str = "zipf", n_invalid: int | None = None,
+                       p_invalid: float = 0.01, nthreads=None) -> AttestWorkload:
+    """Paper-form transactions.  Payload lengths default to U{130..154}: the paper's
+    220-244-byte transactions less the 90-byte attestation (Table 3)."""
+    ss = np.random.SeedSequence(seed)
+    (r_rev, r_dom, r_idu, r_perm, r_len, r_msg, r_bad, r_kind, r_bit,
+     r_wk) = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(10)]
+    rev = r_rev.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    domain = r_dom.integers(0, 256, size=8, dtype=np.uint8).tobytes()
+    if id_dist == "zipf":
+        ids = zipf_ids(r_idu, r_perm, n, n_id, 1.1)
+    else:
+        ids = r_idu.integers(0, n_id, size=n, dtype=np.uint32)
+    if lengths is None:
+        L = r_len.integers(130, 155, size=n).astype(np.int64)
+    elif callable(lengths):
+        L = np.asarray(lengths(r_len, n), dtype=np.int64)
+    else:
+        L = np.full(n, int(lengths), np.int64) if np.isscalar(lengths) else np.asarray(lengths)
+    poff = np.zeros(n + 1, np.uint64)
+    np.cumsum(L, out=poff[1:])
+    payload = r_msg.integers(0, 256, size=int(poff[-1]), dtype=np.uint8)
+    keys = client_keys(rev, domain, INFO_ATTEST, nthreads)
+    obj = client_digest(payload, poff, nthreads)
+    dom = np.frombuffer(domain, np.uint8)
+    msgs = np.concatenate([obj, np.repeat(dom[None, :], n, axis=0)], axis=1).reshape(-1)
+    moff = np.arange(n + 1, dtype=np.uint64) * 40
+
+    if n_invalid is None:
+        n_invalid = int(np.floor(p_invalid * n + 0.5))
+    bad = r_bad.choice(n, size=n_invalid, replace=False) if n_invalid else np.zeros(0, np.int64)
+    kinds = (P_PAYLOAD, P_OBJHASH, P_DOMAIN, P_CRED, P_KEY)
+    kind = np.asarray(kinds)[r_kind.integers(0, len(kinds), size=n_invalid)]
+    kind = np.where((kind == P_PAYLOAD) & (L[bad] == 0), P_CRED, kind)
+    key_index = ids.copy()
+    wk = bad[kind == P_KEY]
+    if wk.size:
+        other = r_wk.integers(0, n_id - 1, size=wk.size, dtype=np.int64)
+        other = other + (other >= ids[wk])
+        key_index[wk] = other.astype(np.uint32)
+    cred = client_sign(keys, msgs, moff, key_index, nthreads)
+    att = np.concatenate([obj, np.repeat(dom[None, :], n, axis=0), cred], axis=1)
+    # flips after signing: payload (binding fails), obj_hash, domain, credential
+    field_bits = np.select([kind == P_PAYLOAD, kind == P_OBJHASH, kind == P_DOMAIN, kind == P_CRED],
+                           [8 * L[bad], 256, 64, 256], 1)
+    bit = r_bit.integers(0, np.maximum(field_bits, 1), dtype=np.int64) if n_invalid else \
+        np.zeros(0, np.int64)
+    for code, base in ((P_OBJHASH, 0), (P_DOMAIN, 32), (P_CRED, 40)):
+        sel = kind == code
+        att[bad[sel], base + bit[sel] // 8] ^= (1 << (bit[sel] % 8)).astype(np.uint8)
+    sel = kind == P_PAYLOAD
+    np.bitwise_xor.at(payload, poff[bad[sel]].astype(np.int64) + bit[sel] // 8,
+                      (1 << (bit[sel] % 8)).astype(np.uint8))
+    truth = np.ones(n, bool)
+    truth[bad] = False
+    return AttestWorkload("paper-form-%d" % n, rev, domain, INFO_ATTEST, payload, poff,
+                          ids.astype(np.uint32), att, truth, keys,
+                          dict(seed=seed, bad=bad, bad_kind=kind))

@@ -301,3 +301,72 @@ def test_every_single_bit_flip_is_rejected():
                                               np.frombuffer(tag * 256, np.uint8).reshape(256, 32))
         assert count == 0, j
     assert ok_total == 64
+
+
+# ---------------------------------------------------------------- paper-form attestations
+def _bits(mask, n):
+    return np.unpackbits(np.asarray(mask, np.uint32).view(np.uint8), bitorder="little")[:n]
+
+
+def _attest_by_hashlib(keys, payload, poff, ids, att):
+    """Validity of each paper-form record from hashlib/hmac alone (no oracle code)."""
+    out = np.zeros(ids.shape[0], bool)
+    for i in range(ids.shape[0]):
+        a, b = int(poff[i]), int(poff[i + 1])
+        if ids[i] >= keys.shape[0] or b < a:
+            continue
+        rec = att[i].tobytes()
+        bound = hashlib.sha256(payload[a:b].tobytes()).digest() == rec[:32]
+        cred = hmac.digest(keys[ids[i]].tobytes(), rec[:40], "sha256") == rec[40:]
+        out[i] = bound and cred
+    return out
+
+
+def test_attest_matches_truth_and_hashlib():
+    w = W.paper_attestations(n=3000, n_id=512, n_invalid=300)
+    keys = oracle.derive_keys(w.rev, w.domain, W.INFO_ATTEST, nthreads=4)
+    assert (keys == w.keys).all()      # oracle HKDF == OpenSSL HKDF with the domain as salt
+    mask, count = oracle.verify_attest(keys, w.payload, w.poff, w.ids, w.att, nthreads=4)
+    assert count == 3000 - 300 == int(w.truth.sum())
+    assert (mask == w.truth_bitmask()).all()
+    ref = _attest_by_hashlib(keys, w.payload, w.poff, w.ids, w.att)
+    assert (ref == w.truth).all()
+    # every corruption kind occurred
+    assert set(map(int, w.meta["bad_kind"])) == {W.P_PAYLOAD, W.P_OBJHASH, W.P_DOMAIN, W.P_CRED,
+                                                 W.P_KEY}
+
+
+def test_attest_single_bit_flips_and_special_cases():
+    r = _rng(21)
+    w = W.paper_attestations(n=8, n_id=8, n_invalid=0, seed=77)
+    keys = w.keys
+    for i in range(w.n):
+        a, b = int(w.poff[i]), int(w.poff[i + 1])
+        pl = w.payload[a:b]
+        variants_p, variants_a = [pl], [w.att[i]]
+        for bit in r.choice(8 * pl.size, size=64, replace=False):   # payload flips
+            p2 = pl.copy(); p2[bit // 8] ^= 1 << (bit % 8)
+            variants_p.append(p2); variants_a.append(w.att[i])
+        for bit in range(8 * 72):                                  # every record bit
+            a2 = w.att[i].copy(); a2[bit // 8] ^= 1 << (bit % 8)
+            variants_p.append(pl); variants_a.append(a2)
+        n = len(variants_p)
+        poff = np.zeros(n + 1, np.uint64)
+        np.cumsum([v.size for v in variants_p], out=poff[1:])
+        mask, count = oracle.verify_attest(keys, np.concatenate(variants_p), poff,
+                                           np.full(n, w.ids[i], np.uint32), np.stack(variants_a))
+        bits = _bits(mask, n)
+        assert bits[0] == 1 and count == 1, i
+    # empty payload (binding to SHA-256 of the empty string), unregistered id, bad offsets
+    dom = w.domain
+    obj = hashlib.sha256(b"").digest()
+    cred = hmac.digest(keys[0].tobytes(), obj + dom, "sha256")
+    att = np.frombuffer((obj + dom + cred) * 3, np.uint8).reshape(3, 72)
+    ids = np.array([0, 8, 0xFFFFFFFF], np.uint32)
+    mask, count = oracle.verify_attest(keys, np.zeros(0, np.uint8), np.zeros(4, np.uint64), ids,
+                                       att)
+    assert count == 1 and mask[0] == 1
+    poff = np.array([5, 5, 0, 0], np.uint64)            # record 1 has decreasing offsets
+    mask, count = oracle.verify_attest(keys, np.zeros(8, np.uint8), poff,
+                                       np.zeros(3, np.uint32), att)
+    assert list(_bits(mask, 3)) == [1, 0, 1] and count == 2
