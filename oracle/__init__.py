@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     hmac_midstates,
     hkdf_sha256,
     derive_keys,
+    derive_keys_multi,
     verify_batch,
     verify_batch_rev,
     verify_attest,

@@ -132,6 +132,16 @@ def derive_keys(rev: np.ndarray, salt: bytes, info: bytes, nthreads: int = 1) ->
     return keys
 
 
+def derive_keys_multi(rev: np.ndarray, streams, nthreads: int = 1) -> np.ndarray:
+    """Keys of several HKDF streams (Def. 2.1: one root entropy, one key per
+    (salt, info) purpose): out[s][j] = HKDF(salt_s, IKM = rev[j], info_s, 32)."""
+    rev = np.ascontiguousarray(rev, dtype=np.uint8).reshape(-1, 32)
+    out = np.zeros((len(streams), rev.shape[0], 32), np.uint8)
+    for s, (salt, info) in enumerate(streams):
+        out[s] = derive_keys(rev, salt, info, nthreads)
+    return out
+
+
 def verify_batch(keys: np.ndarray, msg: np.ndarray, off: np.ndarray, ids: np.ndarray,
                  tags: np.ndarray, nthreads: int = 1) -> tuple[np.ndarray, int]:
     """Bitmask (u32 words, LSB-first) and valid count for one block of txs."""

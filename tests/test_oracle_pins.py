@@ -370,3 +370,25 @@ def test_attest_single_bit_flips_and_special_cases():
     mask, count = oracle.verify_attest(keys, np.zeros(8, np.uint8), poff,
                                        np.zeros(3, np.uint32), att)
     assert list(_bits(mask, 3)) == [1, 0, 1] and count == 2
+
+
+# ---------------------------------------------------------------- several key streams
+def _info_strings():
+    return [l.split("\t")[1].encode() for l in
+            open(__file__.replace("test_oracle_pins.py", "golden/info_strings.tsv"))
+            .read().splitlines() if l and not l.startswith("#")]
+
+
+def test_multi_stream_keys_against_openssl():
+    """Every purpose string of the paper (golden file) and per-slot domains as
+    salts: each stream's keys equal OpenSSL's HKDF, and no two keys coincide."""
+    r = _rng(31)
+    rev = r.integers(0, 256, size=(200, 32), dtype=np.uint8)
+    streams = [(_bytes(r, 32), info) for info in _info_strings()]
+    streams += [(_bytes(r, 8), W.INFO_ATTEST) for _ in range(3)]     # three slots' domains
+    streams += [(b"", b""), (_bytes(r, 64), b"z" * 64)]
+    out = oracle.derive_keys_multi(rev, streams, nthreads=4)
+    assert out.shape == (len(streams), 200, 32)
+    for s, (salt, info) in enumerate(streams):
+        assert (out[s] == W.client_keys(rev, salt, info)).all(), s
+    assert len({bytes(k) for k in out.reshape(-1, 32)}) == len(streams) * 200
