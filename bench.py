@@ -73,6 +73,16 @@ def counter_traffic():
     return int(fields["traffic_bytes_per_launch"])
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, seconds: float) -> dict:
     """The CPU oracle as it stands on this host: all keys, then a prefix sample of txs."""
     import oracle
@@ -94,10 +104,30 @@ def cpu_baseline(w, seconds: float) -> dict:
     if sample % 32 == 0 and not np.array_equal(mask, truth):
         raise SystemExit("oracle disagrees with the generator's truth mask")
     step_s = t_derive + t_verify * (w.n / sample)
+    # one thread, for the per-transaction cost the paper quotes for one core
+    one = min(w.n, 50_000)
+    t = time.perf_counter()
+    oracle.verify_batch(keys, w.msg, w.off[: one + 1], w.ids[:one], w.tags[:one], 1)
+    us_per_tx_1t = (time.perf_counter() - t) / one * 1e6
     return {"value": w.n / step_s, "unit": "attestations/s", "cores": threads, "kind": "oracle",
             "sample": "HKDF for all %d identities (%.2f s) + HMAC verify of the first %d of %d txs "
                       "(%.2f s), verify time scaled to the whole batch" %
-                      (w.n_id, t_derive, sample, w.n, t_verify)}
+                      (w.n_id, t_derive, sample, w.n, t_verify),
+            "single_thread_us_per_tx": us_per_tx_1t,
+            "host_cpu": host_cpu_model()}
+
+
+def measured_valu_rate(ace, torch) -> dict:
+    """The device's INT32 VALU issue rate from the library's probe kernel, beside
+    the peak the roofline uses (the probe runs after the timed steps)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rates = [ace.valu_rate(iters=20000, wgs_per_cu=8) for _ in range(3)]
+    best = max(rates) / 1e12
+    log("VALU probe: %.2f T lane-instr/s measured (%d CUs, implied clock %.2f GHz), "
+        "peak used %.2f" % (best, cus, best * 1e3 / (cus * 64), PEAK_INT32_TOPS))
+    return {"measured": best, "unit": "T int32 lane-instr/s", "cus": cus,
+            "implied_clock_ghz": best * 1e3 / (cus * 64), "peak_used": PEAK_INT32_TOPS,
+            "probe": "8 WGs x 256 lanes per CU, 20000 x 192 alignbit/bitop3/add3 each, best of 3"}
 
 
 def time_calls(fn, steps: int, warmup: int):
@@ -642,6 +672,7 @@ def main() -> int:
         "tuning": ace.get_tuning(),
         "tuning_source": "autotuned" if tuned else "library defaults",
     }
+    result["valu_rate"] = measured_valu_rate(ace, torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (about %.0f s)" % args.cpu_seconds)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

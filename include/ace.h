@@ -93,6 +93,36 @@ ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *
                             size_t salt_len, const uint8_t *h_info, size_t info_len,
                             uint8_t *d_key_out, uint32_t *d_mid_out, void *stream);
 
+/*
+ * ace_derive_keys_multi -- the keys of several HKDF streams for one registry:
+ * the purpose streams of Def. 2.1 (one key per purpose string from the same
+ * root entropy), the validator keys of the consensus and vote equations
+ * (valkey, votekey), or the attestation keys of several slots (eq. attestkey,
+ * one domain each).  For stream s and identity j
+ *   k[s][j] = HKDF-SHA256(salt_s, IKM = REV_j, info_s, L = 32)
+ * and, when d_mid_out is given, its HMAC midstates.
+ *   h_streams  n_streams (salt, info) pairs in host memory, read before the
+ *              call returns; salt_len <= ACE_MULTI_MAX_SALT_BYTES and
+ *              info_len <= ACE_MULTI_MAX_INFO_BYTES (longer ones: one
+ *              ace_derive_keys call per stream); salt_len 0 means HashLen zero
+ *              bytes.
+ *   d_key_out  [n_streams][n_id][32] bytes or NULL.
+ *   d_mid_out  [n_streams][n_id][16] uint32 or NULL (not both NULL).
+ * n_id == 0 or n_streams == 0 is a no-op.  Needs no workspace.
+ */
+#define ACE_MULTI_MAX_SALT_BYTES 64u
+#define ACE_MULTI_MAX_INFO_BYTES 64u
+typedef struct {
+    const uint8_t *h_salt;
+    size_t salt_len;
+    const uint8_t *h_info;
+    size_t info_len;
+} ace_hkdf_stream;
+
+ACE_API int ace_derive_keys_multi(const uint8_t *d_rev, uint32_t n_id,
+                                  const ace_hkdf_stream *h_streams, uint32_t n_streams,
+                                  uint8_t *d_key_out, uint32_t *d_mid_out, void *stream);
+
 /* One block of transactions (Alg. 1 SelectTransactions output). */
 typedef struct {
     const uint8_t *d_msg;    /* messages back to back; may be NULL only if n_tx == 0      */
@@ -299,6 +329,19 @@ typedef struct {
 
 ACE_API int ace_profile_enable(int on);
 ACE_API int ace_profile_read(ace_profile *out, int reset);
+
+/*
+ * ace_valu_rate -- measurement aid, not a step of the method: the INT32 VALU
+ * issue rate the verify kernels are priced against.  Launches wgs_per_cu
+ * workgroups of 256 lanes per CU, each lane running `iters` x 192 dependent
+ * alignbit / bitop3 / add3 instructions (eight independent chains), times the
+ * launch with HIP events on `stream`, waits for it, and stores lane
+ * instructions per second in *out_lane_instr_per_s.  d_sink: 4 bytes of
+ * device memory the kernel never writes in practice (it keeps the compiler
+ * from removing the work).  iters >= 1, wgs_per_cu in 1..64.
+ */
+ACE_API int ace_valu_rate(uint32_t iters, uint32_t wgs_per_cu, uint32_t *d_sink,
+                          double *out_lane_instr_per_s, void *stream);
 
 #ifdef __cplusplus
 }

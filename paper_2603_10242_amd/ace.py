@@ -55,6 +55,11 @@ class ace_keyset(ctypes.Structure):
                 ("info_len", ctypes.c_size_t)]
 
 
+class ace_hkdf_stream(ctypes.Structure):
+    _fields_ = [("h_salt", ctypes.c_void_p), ("salt_len", ctypes.c_size_t),
+                ("h_info", ctypes.c_void_p), ("info_len", ctypes.c_size_t)]
+
+
 class ace_tuning(ctypes.Structure):
     _fields_ = [("binned_min_tx", ctypes.c_uint64), ("verify_wgs_per_cu", ctypes.c_uint32),
                 ("aux_wgs_per_cu", ctypes.c_uint32), ("auto_persistent", ctypes.c_uint32)]
@@ -88,6 +93,11 @@ def load(path: str = LIB_PATH):
     lib.ace_verify_batch.argtypes = [ctypes.POINTER(ace_keyset), ctypes.POINTER(ace_block), u32,
                                      vp, sz, u32, vp]
     lib.ace_verify_batch.restype = ctypes.c_int
+    lib.ace_derive_keys_multi.argtypes = [vp, u32, ctypes.POINTER(ace_hkdf_stream), u32, vp, vp,
+                                          vp]
+    lib.ace_derive_keys_multi.restype = ctypes.c_int
+    lib.ace_valu_rate.argtypes = [u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.ace_valu_rate.restype = ctypes.c_int
     lib.ace_verify_attestations.argtypes = lib.ace_verify_batch.argtypes
     lib.ace_verify_attestations.restype = ctypes.c_int
     lib.ace_get_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
@@ -210,6 +220,23 @@ def derive_keys(rev: torch.Tensor, salt: bytes, info: bytes, key_out: Optional[t
                                   _ptr(mid_out), _stream(stream)))
 
 
+def derive_keys_multi(rev: torch.Tensor, streams: Sequence[tuple[bytes, bytes]],
+                      key_out: Optional[torch.Tensor] = None,
+                      mid_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """ace_derive_keys_multi: keys [S][n_id][32] and/or midstates [S][n_id][16]
+    of S (salt, info) streams."""
+    n_id = int(rev.shape[0]) if rev is not None else 0
+    keep = []
+    arr = (ace_hkdf_stream * max(1, len(streams)))()
+    for k, (salt, info) in enumerate(streams):
+        sb = ctypes.create_string_buffer(salt, max(1, len(salt)))
+        ib = ctypes.create_string_buffer(info, max(1, len(info)))
+        keep += [sb, ib]
+        arr[k] = ace_hkdf_stream(ctypes.addressof(sb), len(salt), ctypes.addressof(ib), len(info))
+    _check(load().ace_derive_keys_multi(_ptr(rev) if n_id else None, n_id, arr, len(streams),
+                                        _ptr(key_out), _ptr(mid_out), _stream(stream)))
+
+
 def _blocks_array(blocks: Sequence[DeviceBlock]):
     arr = (ace_block * max(1, len(blocks)))()
     for i, b in enumerate(blocks):
@@ -252,6 +279,15 @@ def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
                         stream=None) -> torch.Tensor:
     """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
     return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream)
+
+
+def valu_rate(iters: int = 20000, wgs_per_cu: int = 8, stream=None) -> float:
+    """ace_valu_rate: measured INT32 VALU lane instructions per second."""
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = ctypes.c_double()
+    _check(load().ace_valu_rate(iters, wgs_per_cu, _ptr(sink), ctypes.byref(out),
+                                _stream(stream)))
+    return out.value
 
 
 def midstate_keyset(rev: torch.Tensor, salt: bytes, info: bytes, stream=None) -> DeviceKeyset:

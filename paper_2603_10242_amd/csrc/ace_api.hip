@@ -16,6 +16,7 @@
 
 // The kernels are compiled in this translation unit.
 #include "ace_kernels.hip"
+#include "valu_rate.hip"
 
 using namespace ace;
 
@@ -448,6 +449,37 @@ ACE_API const char *ace_last_error(void) { return g_err; }
 
 ACE_API const char *ace_version(void) { return "ace 0.2 gfx950"; }
 
+ACE_API int ace_valu_rate(uint32_t iters, uint32_t wgs_per_cu, uint32_t *d_sink,
+                          double *out_lane_instr_per_s, void *stream)
+{
+    clear_error();
+    if (!out_lane_instr_per_s || !d_sink) return fail(ACE_ERR_INVALID_ARG, "NULL output");
+    if (!aligned(d_sink, 4)) return fail(ACE_ERR_INVALID_ARG, "d_sink not 4-byte aligned");
+    if (iters < 1 || wgs_per_cu < 1 || wgs_per_cu > 64)
+        return fail(ACE_ERR_INVALID_ARG, "iters >= 1 and wgs_per_cu in 1..64");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const unsigned g = (unsigned)cu_count() * wgs_per_cu;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = check_hip(hipEventCreate(&ev[0]), "hipEventCreate");
+    if (!rc) rc = check_hip(hipEventCreate(&ev[1]), "hipEventCreate");
+    if (!rc) rc = check_hip(hipEventRecord(ev[0], s), "hipEventRecord");
+    if (!rc) {
+        hipLaunchKernelGGL(k_valu_rate, dim3(g), dim3(256), 0, s, iters, 1u, d_sink);
+        rc = launch_status("k_valu_rate launch");
+    }
+    if (!rc) rc = check_hip(hipEventRecord(ev[1], s), "hipEventRecord");
+    if (!rc) rc = check_hip(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+    float ms = 0.f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+    for (hipEvent_t e : ev)
+        if (e) hipEventDestroy(e);
+    if (rc) return rc;
+    const double lanes = (double)g * 256.0;
+    const double instr = (double)iters * kValuStepsPerIter * kValuOpsPerStep;
+    *out_lane_instr_per_s = ms > 0.f ? lanes * instr / (ms * 1e-3) : 0.0;
+    return ACE_OK;
+}
+
 ACE_API int ace_get_tuning(ace_tuning *out)
 {
     clear_error();
@@ -485,6 +517,47 @@ ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *
     const unsigned grid = (unsigned)((n_id + kWG - 1) / kWG);
     hipLaunchKernelGGL(k_derive, dim3(grid), dim3(kWG), 0, s, d_rev, n_id, d_key_out, d_mid_out, hp);
     return launch_status("k_derive launch");
+}
+
+ACE_API int ace_derive_keys_multi(const uint8_t *d_rev, uint32_t n_id,
+                                  const ace_hkdf_stream *h_streams, uint32_t n_streams,
+                                  uint8_t *d_key_out, uint32_t *d_mid_out, void *stream)
+{
+    clear_error();
+    if (!d_key_out && !d_mid_out) return fail(ACE_ERR_INVALID_ARG, "d_key_out and d_mid_out are both NULL");
+    if (n_streams && !h_streams) return fail(ACE_ERR_INVALID_ARG, "h_streams is NULL");
+    for (uint32_t k = 0; k < n_streams; ++k) {
+        const ace_hkdf_stream &t = h_streams[k];
+        if (t.salt_len > kMultiSalt || t.info_len > kMultiInfo)
+            return fail(ACE_ERR_INVALID_ARG, "stream %u: salt_len %zu / info_len %zu exceed %u / %u", k,
+                        t.salt_len, t.info_len, kMultiSalt, kMultiInfo);
+        if ((t.salt_len && !t.h_salt) || (t.info_len && !t.h_info))
+            return fail(ACE_ERR_INVALID_ARG, "stream %u: NULL salt or info with nonzero length", k);
+    }
+    if (n_id == 0 || n_streams == 0) return ACE_OK;
+    if (!d_rev) return fail(ACE_ERR_INVALID_ARG, "d_rev is NULL");
+    if (!aligned(d_rev, 4) || (d_key_out && !aligned(d_key_out, 4)) || (d_mid_out && !aligned(d_mid_out, 4)))
+        return fail(ACE_ERR_INVALID_ARG, "misaligned device array");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const unsigned gx = (unsigned)((n_id + kWG - 1) / kWG);
+    for (uint32_t first = 0; first < n_streams; first += kMultiStreams) {
+        MultiHkdf mp;
+        memset(&mp, 0, sizeof mp);
+        mp.first = first;
+        mp.count = std::min<uint32_t>(kMultiStreams, n_streams - first);
+        for (uint32_t y = 0; y < mp.count; ++y) {
+            const ace_hkdf_stream &t = h_streams[first + y];
+            mp.s[y].salt_len = (uint32_t)t.salt_len;
+            mp.s[y].info_len = (uint32_t)t.info_len;
+            if (t.salt_len) memcpy(mp.s[y].salt, t.h_salt, t.salt_len);
+            if (t.info_len) memcpy(mp.s[y].info, t.h_info, t.info_len);
+        }
+        hipLaunchKernelGGL(k_derive_multi, dim3(gx, mp.count), dim3(kWG), 0, s, d_rev, n_id, d_key_out,
+                           d_mid_out, mp);
+        int rc = launch_status("k_derive_multi launch");
+        if (rc) return rc;
+    }
+    return ACE_OK;
 }
 
 ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,

@@ -72,6 +72,23 @@ struct HkdfParams {
     uint8_t info[kMaxInfo + 1];
 };
 
+// Several HKDF parameter sets in one launch (one per grid row): short salts
+// and infos only, so that the set fits the kernel's argument block.
+constexpr uint32_t kMultiStreams = 8;
+constexpr uint32_t kMultiSalt = 64;
+constexpr uint32_t kMultiInfo = 64;
+struct StreamParams {
+    uint32_t salt_len;
+    uint32_t info_len;
+    uint8_t salt[kMultiSalt];
+    uint8_t info[kMultiInfo];
+};
+struct MultiHkdf {
+    uint32_t first;  // index of s[0] among the call's streams
+    uint32_t count;
+    StreamParams s[kMultiStreams];
+};
+
 // Derived per-workgroup constants of an HKDF parameter set (built in LDS).
 struct HkdfPrep {
     uint32_t salt_ipad[8];

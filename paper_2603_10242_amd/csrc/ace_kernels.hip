@@ -113,7 +113,8 @@ __device__ inline uint32_t padded_word(const uint8_t *p, uint32_t len, uint32_t 
 // Per-workgroup HKDF constants: the salt's HMAC midstates and the padded
 // expand input (info || 0x01), built by wave 0 (all lanes compute the same
 // values) into LDS.
-__device__ void hkdf_prepare(const HkdfParams &hp, HkdfPrep &out)
+template <class Params>
+__device__ void hkdf_prepare(const Params &hp, HkdfPrep &out)
 {
     uint32_t k0[16];
     const uint32_t sl = hp.salt_len;
@@ -241,15 +242,13 @@ __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], 
 // ------------------------------------------------------------------------------------------
 // k_derive: one identity per lane.
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
+// Key and midstates of identity j under the prepared parameter set; outputs
+// go to row `row` of key_out / mid_out.
+__device__ __forceinline__ void derive_identity(const uint8_t *__restrict__ rev, uint32_t n_id,
+                                                uint32_t j, uint64_t row, const HkdfPrep &prep,
                                                 uint8_t *__restrict__ key_out,
-                                                uint32_t *__restrict__ mid_out, HkdfParams hp)
+                                                uint32_t *__restrict__ mid_out)
 {
-    __shared__ HkdfPrep prep;
-    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
-    __syncthreads();
-
-    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
     const bool live = j < n_id;
     uint32_t rv[8];
     if (live) {
@@ -266,15 +265,41 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__re
     derive_lane(live, rv, prep, key, kip, kop);
     if (!live) return;
     if (key_out) {
-        uint32_t *q = reinterpret_cast<uint32_t *>(key_out + 32ull * j);
+        uint32_t *q = reinterpret_cast<uint32_t *>(key_out + 32ull * row);
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[i] = bswap32(key[i]);
     }
     if (mid_out) {
-        uint32_t *q = mid_out + 16ull * j;
+        uint32_t *q = mid_out + 16ull * row;
 #pragma unroll
         for (int i = 0; i < 8; ++i) { q[i] = kip.h[i]; q[8 + i] = kop.h[i]; }
     }
+}
+
+__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
+                                                uint8_t *__restrict__ key_out,
+                                                uint32_t *__restrict__ mid_out, HkdfParams hp)
+{
+    __shared__ HkdfPrep prep;
+    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
+    __syncthreads();
+    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
+    derive_identity(rev, n_id, j, j, prep, key_out, mid_out);
+}
+
+// k_derive_multi: grid row y derives every identity's key under parameter set
+// first + y (Def. 2.1's purpose streams, per-slot domains); output row
+// (first + y) * n_id + j.
+__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive_multi(const uint8_t *__restrict__ rev,
+                                                      uint32_t n_id, uint8_t *__restrict__ key_out,
+                                                      uint32_t *__restrict__ mid_out, MultiHkdf mp)
+{
+    __shared__ HkdfPrep prep;
+    const uint32_t y = blockIdx.y;
+    if (threadIdx.x < 64) hkdf_prepare(mp.s[y], prep);
+    __syncthreads();
+    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
+    derive_identity(rev, n_id, j, (uint64_t)(mp.first + y) * n_id + j, prep, key_out, mid_out);
 }
 
 // ------------------------------------------------------------------------------------------

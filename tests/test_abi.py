@@ -123,6 +123,28 @@ def test_derive_argument_errors(lib):
     assert lib.ace_derive_keys(None, 0, salt, 32, info, 16, 0x2000, None, None) == ace.ACE_OK
 
 
+def test_derive_multi_argument_errors(lib):
+    from paper_2603_10242_amd import ace
+    salt = ctypes.create_string_buffer(b"s" * 80)
+    info = ctypes.create_string_buffer(b"i" * 80)
+    arr = (ace.ace_hkdf_stream * 2)()
+    arr[0] = ace.ace_hkdf_stream(ctypes.addressof(salt), 32, ctypes.addressof(info), 23)
+    arr[1] = ace.ace_hkdf_stream(ctypes.addressof(salt), 65, ctypes.addressof(info), 23)
+    # second stream's salt too long: nothing launched for the first either
+    assert lib.ace_derive_keys_multi(0x1000, 4, arr, 2, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    arr[1] = ace.ace_hkdf_stream(ctypes.addressof(salt), 8, ctypes.addressof(info), 65)
+    assert lib.ace_derive_keys_multi(0x1000, 4, arr, 2, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    arr[1] = ace.ace_hkdf_stream(None, 8, ctypes.addressof(info), 8)
+    assert lib.ace_derive_keys_multi(0x1000, 4, arr, 2, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    arr[1] = ace.ace_hkdf_stream(ctypes.addressof(salt), 64, ctypes.addressof(info), 64)
+    assert lib.ace_derive_keys_multi(0x1000, 4, arr, 2, None, None, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_derive_keys_multi(0x1000, 4, None, 2, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_derive_keys_multi(None, 4, arr, 2, 0x2000, None, None) == ace.ACE_ERR_INVALID_ARG
+    # nothing to do: no launch
+    assert lib.ace_derive_keys_multi(None, 0, arr, 2, 0x2000, None, None) == ace.ACE_OK
+    assert lib.ace_derive_keys_multi(None, 4, arr, 0, 0x2000, None, None) == ace.ACE_OK
+
+
 def test_workspace_size_layout(lib):
     from paper_2603_10242_amd import ace
     ks, keep = _keyset(ace)
@@ -172,3 +194,25 @@ def test_graph_argument_errors(lib):
                                 ctypes.byref(out)) == ace.ACE_ERR_INVALID_ARG
     assert lib.ace_graph_launch(None, None, 0, None) == ace.ACE_ERR_INVALID_ARG
     assert lib.ace_graph_destroy(None) == ace.ACE_OK
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="hipcc absent")
+def test_valu_probe_loop_is_192_valu_instructions(tmp_path):
+    """The VALU-rate probe prices its launch at 192 lane instructions per loop
+    iteration: the compiled loop body must hold exactly those."""
+    import subprocess
+    src = tmp_path / "probe.hip"
+    src.write_text('#include "%s"\nvoid launch(uint32_t *s) { hipLaunchKernelGGL(ace::k_valu_rate, '
+                   'dim3(1), dim3(256), 0, 0, 10u, 1u, s); }\n'
+                   % os.path.join(ROOT, "paper_2603_10242_amd", "csrc", "valu_rate.hip"))
+    asm = tmp_path / "probe.s"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "--cuda-device-only", "-S", "-o", str(asm), str(src)],
+                          stderr=subprocess.DEVNULL)
+    lines = asm.read_text().splitlines()
+    head = next(i for i, l in enumerate(lines) if "Inner Loop Header" in l)
+    tail = next(i for i in range(head, len(lines)) if "s_cbranch" in lines[i])
+    ops = [l.split()[0] for l in lines[head + 1:tail] if l.strip().startswith("v_")]
+    assert len(ops) == 192
+    assert sorted(set(ops)) == ["v_add3_u32", "v_alignbit_b32", "v_bitop3_b32"]

@@ -99,6 +99,37 @@ def test_derive_keys_match_openssl_client_keys(ace):
     assert np.array_equal(key.cpu().numpy(), w.keys)
 
 
+def _info_strings():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "info_strings.tsv")
+    return [l.split("\t")[1].encode() for l in open(path).read().splitlines()
+            if l and not l.startswith("#")]
+
+
+@pytest.mark.parametrize("n_id", [1, 300, 4097])
+def test_derive_keys_multi(ace, n_id):
+    """Keys and midstates of the paper's purpose streams, the validator streams
+    and eleven slot domains (19 streams: three launches of up to 8)."""
+    import torch
+    note("derive multi n_id=%d" % n_id)
+    r = np.random.Generator(np.random.PCG64(4242 + n_id))
+    rev = r.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    streams = [(r.integers(0, 256, size=32, dtype=np.uint8).tobytes(), i) for i in _info_strings()]
+    streams += [(r.integers(0, 256, size=8, dtype=np.uint8).tobytes(), W.INFO_ATTEST)
+                for _ in range(8)]
+    streams += [(b"", b""), (b"\x07" * 64, b"q" * 64), (b"s", b"i" * 54)]
+    S = len(streams)
+    key = torch.zeros((S, n_id, 32), dtype=torch.uint8, device="cuda")
+    mid = torch.zeros((S, n_id, 16), dtype=torch.int32, device="cuda")
+    ace.derive_keys_multi(ace.to_device(rev), streams, key_out=key, mid_out=mid)
+    torch.cuda.synchronize()
+    want = oracle.derive_keys_multi(rev, streams, nthreads=8)
+    assert np.array_equal(key.cpu().numpy(), want)
+    got_mid = mid.cpu().numpy().view(np.uint32)
+    for s in (0, 7, 9, S - 1):
+        assert np.array_equal(got_mid[s], oracle.hmac_midstates(want[s]))
+
+
 # ------------------------------------------------------------------ the tiny and block workloads
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("keys", ["midstate", "rev", "rev-per-tx"])
@@ -277,3 +308,12 @@ def test_many_blocks_256(ace):
             mask, count = blk.result()
             assert count == int(w.truth[a:b].sum())
             assert np.array_equal(mask, W.pack_bits(w.truth[a:b]))
+
+
+def test_valu_probe_rate_is_plausible(ace):
+    """The probe's measured INT32 VALU rate lies near the 39.32 T peak the
+    roofline uses (256 CUs x 64 lanes x 2.4 GHz)."""
+    note("valu probe")
+    rate = ace.valu_rate(iters=2000, wgs_per_cu=8) / 1e12
+    note("measured %.2f T lane-instr/s" % rate)
+    assert 0.3 * 39.3216 < rate < 1.1 * 39.3216
