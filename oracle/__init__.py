@@ -18,4 +18,5 @@ from .oracle import (  # noqa: F401
     verify_batch,
     verify_batch_rev,
     verify_attest,
+    poh_verify,
 )

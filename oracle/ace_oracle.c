@@ -251,6 +251,8 @@ typedef struct {
     uint32_t *bitmask; uint64_t count;
     /* paper-form attestation */
     const uint8_t *att; /* [n][72]: obj_hash (32) || domain (8) || credential (32) */
+    /* hash-chain segments */
+    const uint8_t *seg_start, *seg_end; const uint32_t *seg_steps;
 } job_t;
 
 /* Full 32-byte compare with no early exit: OR of the XORs of all bytes. */
@@ -271,6 +273,25 @@ static void *run_job(void *arg)
         return NULL;
     }
     uint64_t count = 0;
+    if (j->kind == 3) {
+        /* Sec. "Verifiable Clock via Proof of History": H_{i+1} = SHA-256(H_i)
+         * over the 32 digest bytes; segment i is valid when steps[i] such
+         * hashes lead from its start to its end. */
+        for (size_t i = j->lo; i < j->hi; ++i) {
+            uint8_t h[32], nxt[32];
+            memcpy(h, j->seg_start + 32 * i, 32);
+            for (uint32_t t = 0; t < j->seg_steps[i]; ++t) {
+                oracle_sha256(h, 32, nxt);
+                memcpy(h, nxt, 32);
+            }
+            if (cteq32(h, j->seg_end + 32 * i)) {
+                j->bitmask[i / 32] |= (uint32_t)1 << (i % 32);
+                ++count;
+            }
+        }
+        j->count = count;
+        return NULL;
+    }
     for (size_t i = j->lo; i < j->hi; ++i) {
         int valid = 0;
         uint32_t who = j->id[i];
@@ -370,6 +391,20 @@ void oracle_verify_attest(const uint8_t *keys, uint32_t n_id, const uint8_t *pay
     memset(&t, 0, sizeof t);
     t.kind = 2;
     t.keys = keys; t.n_id = n_id; t.msg = payload; t.off = poff; t.id = id; t.att = att;
+    t.bitmask = bitmask_out;
+    run_split(&t, (size_t)n, nthreads, 32, count_out);
+}
+
+/* Hash-chain segments: bit i set iff SHA-256 applied steps[i] times to
+ * start[i] gives end[i] (32-byte values). */
+void oracle_poh_verify(const uint8_t *start, const uint8_t *end, const uint32_t *steps, uint64_t n,
+                       uint32_t *bitmask_out, uint64_t *count_out, int nthreads)
+{
+    memset(bitmask_out, 0, sizeof(uint32_t) * (size_t)((n + 31) / 32));
+    job_t t;
+    memset(&t, 0, sizeof t);
+    t.kind = 3;
+    t.seg_start = start; t.seg_end = end; t.seg_steps = steps;
     t.bitmask = bitmask_out;
     run_split(&t, (size_t)n, nthreads, 32, count_out);
 }

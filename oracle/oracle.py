@@ -55,6 +55,8 @@ def _load():
                                         ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
     lib.oracle_verify_attest.argtypes = [_u8p, ctypes.c_uint32, _u8p, _u64p, _u32p, _u8p,
                                          ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
+    lib.oracle_poh_verify.argtypes = [_u8p, _u8p, _u32p, ctypes.c_uint64, _u32p, _u64p,
+                                      ctypes.c_int]
     _lib = lib
     return lib
 
@@ -186,4 +188,20 @@ def verify_attest(keys: np.ndarray, payload: np.ndarray, poff: np.ndarray, ids: 
                                  _ptr(p_arg, _u8p), _ptr(poff, _u64p), _ptr(ids, _u32p),
                                  _ptr(att, _u8p) if att.size else None, n, _ptr(mask, _u32p),
                                  ctypes.byref(cnt), nthreads)
+    return mask[: (n + 31) // 32], int(cnt.value)
+
+
+def poh_verify(start: np.ndarray, end: np.ndarray, steps: np.ndarray,
+               nthreads: int = 1) -> tuple[np.ndarray, int]:
+    """Hash-chain segments: bit i iff SHA-256^steps[i](start[i]) == end[i]."""
+    start = np.ascontiguousarray(start, dtype=np.uint8).reshape(-1, 32)
+    end = np.ascontiguousarray(end, dtype=np.uint8).reshape(-1, 32)
+    steps = np.ascontiguousarray(steps, dtype=np.uint32)
+    n = steps.shape[0]
+    assert start.shape[0] == n and end.shape[0] == n
+    mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
+    cnt = ctypes.c_uint64(0)
+    if n:
+        _load().oracle_poh_verify(_ptr(start, _u8p), _ptr(end, _u8p), _ptr(steps, _u32p), n,
+                                  _ptr(mask, _u32p), ctypes.byref(cnt), nthreads)
     return mask[: (n + 31) // 32], int(cnt.value)

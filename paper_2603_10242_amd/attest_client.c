@@ -17,7 +17,7 @@
 #include <string.h>
 
 typedef struct {
-    int kind; /* 0 = keys, 1 = tags, 2 = digests */
+    int kind; /* 0 = keys, 1 = tags, 2 = digests, 3 = hash chains */
     uint64_t lo, hi;
     const uint8_t *rev, *salt, *info;
     size_t slen, ilen;
@@ -27,6 +27,7 @@ typedef struct {
     const uint64_t *off;
     const uint32_t *key_index;
     uint8_t *tags_out;
+    const uint32_t *steps;
     int status;
 } job_t;
 
@@ -85,12 +86,35 @@ static void digest_range(job_t *j)
     }
 }
 
+static void chain_range(job_t *j)
+{
+    EVP_MD *md = EVP_MD_fetch(NULL, "SHA256", NULL);
+    EVP_MD_CTX *ctx = md ? EVP_MD_CTX_new() : NULL;
+    if (!ctx) { j->status = -1; EVP_MD_free(md); return; }
+    for (uint64_t i = j->lo; i < j->hi && !j->status; ++i) {
+        uint8_t h[32];
+        unsigned int outl = 0;
+        memcpy(h, j->msg + 32 * i, 32);
+        for (uint32_t t = 0; t < j->steps[i]; ++t) {
+            if (EVP_DigestInit_ex(ctx, md, NULL) <= 0 || EVP_DigestUpdate(ctx, h, 32) <= 0 ||
+                EVP_DigestFinal_ex(ctx, h, &outl) <= 0 || outl != 32) {
+                j->status = -2;
+                break;
+            }
+        }
+        memcpy(j->tags_out + 32 * i, h, 32);
+    }
+    EVP_MD_CTX_free(ctx);
+    EVP_MD_free(md);
+}
+
 static void *run(void *arg)
 {
     job_t *j = (job_t *)arg;
     if (j->kind == 0) derive_range(j);
     else if (j->kind == 1) sign_range(j);
-    else digest_range(j);
+    else if (j->kind == 2) digest_range(j);
+    else chain_range(j);
     return NULL;
 }
 
@@ -151,5 +175,16 @@ int client_digest(const uint8_t *msg, const uint64_t *off, uint64_t n, uint8_t *
     memset(&t, 0, sizeof t);
     t.kind = 2;
     t.msg = msg; t.off = off; t.tags_out = out;
+    return split(&t, n, nthreads);
+}
+
+/* end[i] = SHA-256 applied steps[i] times to start[i] (32-byte values) via OpenSSL. */
+int client_hash_chain(const uint8_t *start, const uint32_t *steps, uint64_t n, uint8_t *end,
+                      int nthreads)
+{
+    job_t t;
+    memset(&t, 0, sizeof t);
+    t.kind = 3;
+    t.msg = start; t.steps = steps; t.tags_out = end;
     return split(&t, n, nthreads);
 }

@@ -53,6 +53,7 @@ def _lib():
         lib.client_derive_keys.argtypes = [vp, ctypes.c_uint64, vp, sz, vp, sz, vp, ctypes.c_int]
         lib.client_sign.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
         lib.client_digest.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
+        lib.client_hash_chain.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
         _client = lib
     return _client
 
@@ -106,6 +107,20 @@ def client_digest(msg: np.ndarray, off: np.ndarray, nthreads: int | None = None)
                               nthreads or host_threads())
     if rc != 0:
         raise RuntimeError("OpenSSL SHA-256 failed (%d)" % rc)
+    return out
+
+
+def client_hash_chain(start: np.ndarray, steps: np.ndarray, nthreads: int | None = None
+                      ) -> np.ndarray:
+    """end[i] = SHA-256 applied steps[i] times to start[i] (OpenSSL)."""
+    start = np.ascontiguousarray(start, dtype=np.uint8).reshape(-1, 32)
+    steps = np.ascontiguousarray(steps, dtype=np.uint32)
+    out = np.zeros_like(start)
+    if start.shape[0]:
+        rc = _lib().client_hash_chain(start.ctypes.data, steps.ctypes.data, start.shape[0],
+                                      out.ctypes.data, nthreads or host_threads())
+        if rc != 0:
+            raise RuntimeError("OpenSSL SHA-256 failed (%d)" % rc)
     return out
 
 
@@ -407,3 +422,63 @@ def paper_attestations(n: int = 2000, n_id: int = 1 << 16, seed: int = SEED_BASE
     return AttestWorkload("paper-form-%d" % n, rev, domain, INFO_ATTEST, payload, poff,
                           ids.astype(np.uint32), att, truth, keys,
                           dict(seed=seed, bad=bad, bad_kind=kind))
+
+
+# ------------------------------------------------------------------ hash-chain segments
+@dataclasses.dataclass
+class ChainWorkload:
+    name: str
+    start: np.ndarray     # [n][32]
+    end: np.ndarray       # [n][32]
+    steps: np.ndarray     # u32 [n]
+    truth: np.ndarray
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.steps.shape[0])
+
+    def truth_bitmask(self) -> np.ndarray:
+        return pack_bits(self.truth)
+
+
+def poh_segments(n: int = 65536, steps=4096, seed: int = SEED_BASE + 7, chained: bool = False,
+                 n_invalid: int | None = None, p_invalid: float = 0.005,
+                 nthreads=None) -> ChainWorkload:
+    """Segments of a SHA-256 hash chain (the clock of the consensus section):
+    a checkpoint every `steps` hashes (an int, or one count per segment).
+    chained=True draws one chain H_0 .. and cuts it at the checkpoints (end[i]
+    == start[i+1]); otherwise every segment starts from its own random value,
+    which has the same per-segment work and can be generated in parallel.
+    Invalid segments: a bit of the end checkpoint flipped, or one step too few."""
+    ss = np.random.SeedSequence(seed)
+    r_start, r_bad, r_kind, r_bit = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(4)]
+    st = (np.full(n, int(steps), np.uint32) if np.isscalar(steps)
+          else np.asarray(steps, np.uint32).copy())
+    if chained:
+        import hashlib
+        start = np.zeros((n, 32), np.uint8)
+        end = np.zeros((n, 32), np.uint8)
+        h = r_start.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+        for i in range(n):
+            start[i] = np.frombuffer(h, np.uint8)
+            for _ in range(int(st[i])):
+                h = hashlib.sha256(h).digest()
+            end[i] = np.frombuffer(h, np.uint8)
+    else:
+        start = r_start.integers(0, 256, size=(n, 32), dtype=np.uint8)
+        end = client_hash_chain(start, st, nthreads)
+    if n_invalid is None:
+        n_invalid = int(np.floor(p_invalid * n + 0.5))
+    bad = r_bad.choice(n, size=n_invalid, replace=False) if n_invalid else np.zeros(0, np.int64)
+    kind = r_kind.integers(0, 2, size=n_invalid)
+    kind = np.where(st[bad] == 0, 0, kind)      # a zero-step segment cannot lose a step
+    bit = r_bit.integers(0, 256, size=n_invalid)
+    end = end.copy()
+    flip = bad[kind == 0]
+    end[flip, bit[kind == 0] // 8] ^= (1 << (bit[kind == 0] % 8)).astype(np.uint8)
+    st[bad[kind == 1]] += 1    # the claimed count is one more than the hashes that lead there
+    truth = np.ones(n, bool)
+    truth[bad] = False
+    return ChainWorkload("poh-%d" % n, start, end, st, truth,
+                         dict(seed=seed, chained=chained, bad=bad, bad_kind=kind))

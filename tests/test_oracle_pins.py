@@ -392,3 +392,47 @@ def test_multi_stream_keys_against_openssl():
     for s, (salt, info) in enumerate(streams):
         assert (out[s] == W.client_keys(rev, salt, info)).all(), s
     assert len({bytes(k) for k in out.reshape(-1, 32)}) == len(streams) * 200
+
+
+# ---------------------------------------------------------------- hash-chain segments
+def test_poh_segments_against_hashlib_chain():
+    """One chain drawn with hashlib, cut at checkpoints of varying step counts
+    (0 included): the oracle accepts exactly the uncorrupted segments, and a
+    corrupted checkpoint shared by two segments breaks both."""
+    r = _rng(41)
+    steps = r.integers(0, 40, size=120).astype(np.uint32)
+    w = W.poh_segments(n=120, steps=steps, chained=True, n_invalid=0, seed=41)
+    assert (w.start[1:] == w.end[:-1]).all()
+    h = w.start[0].tobytes()
+    for i in range(120):           # the chain itself, independently of the generator's loop
+        assert h == w.start[i].tobytes()
+        for _ in range(int(steps[i])):
+            h = hashlib.sha256(h).digest()
+    mask, count = oracle.poh_verify(w.start, w.end, w.steps)
+    assert count == 120 and (mask == W.pack_bits(np.ones(120, bool))).all()
+    # corrupt checkpoint 50 (end of segment 49 = start of segment 50)
+    start, end = w.start.copy(), w.end.copy()
+    end[49, 3] ^= 0x10
+    start[50] = end[49]
+    mask, count = oracle.poh_verify(start, end, w.steps)
+    bits = _bits(mask, 120)
+    expect = np.ones(120, bool)
+    expect[49] = False
+    # segment 50 now starts from the corrupted value: broken unless it has no steps,
+    # in which case its start and end are equal only if end[50] was corrupted alike
+    expect[50] = (start[50] == end[50]).all() if w.steps[50] == 0 else False
+    assert (bits.astype(bool) == expect).all()
+    # a segment of zero steps is valid iff its ends are equal
+    z = np.zeros((2, 32), np.uint8)
+    z[1, 0] = 1
+    mask, count = oracle.poh_verify(z[[0, 0]], z, np.zeros(2, np.uint32))
+    assert list(_bits(mask, 2)) == [1, 0] and count == 1
+
+
+def test_poh_segments_match_truth_and_openssl():
+    w = W.poh_segments(n=2000, steps=97, n_invalid=40, seed=43)
+    mask, count = oracle.poh_verify(w.start, w.end, w.steps, nthreads=4)
+    assert count == 2000 - 40 == int(w.truth.sum())
+    assert (mask == w.truth_bitmask()).all()
+    # both corruption kinds occurred; one step too few is rejected like a flipped bit
+    assert set(map(int, w.meta["bad_kind"])) == {0, 1}
