@@ -434,6 +434,59 @@ def bench_attest(args) -> dict:
     return result
 
 
+def bench_poh(args) -> dict:
+    """Hash-chain segment verification: --poh-segments segments of --poh-steps
+    hashes each, one compression per hash."""
+    from paper_2603_10242_amd import workload as W
+    n, T = args.poh_segments, args.poh_steps
+    log("generating %d chain segments of %d hashes" % (n, T))
+    w = W.poh_segments(n=n, steps=T, step_errors=False)
+    import torch
+    from paper_2603_10242_amd import ace
+    ace.load()
+    torch.cuda.set_device(0)
+    s, e = ace.to_device(w.start), ace.to_device(w.end)
+    mask = torch.zeros(((n + 31) // 32,), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    ace.poh_verify(s, e, T, mask, cnt)
+    torch.cuda.synchronize()
+    if int(cnt.item()) != int(w.truth.sum()) or not np.array_equal(
+            mask.cpu().numpy().view(np.uint32), w.truth_bitmask()):
+        raise SystemExit("RESULT MISMATCH")
+    log("first call bit-exact with the generator's truth mask")
+    ms, ev = time_calls(lambda: ace.poh_verify(s, e, T, mask, cnt), args.steps, args.warmup)
+    comp = n * T
+    achieved = comp * I_REF / (np.median(ev) / 1e3) / 1e12
+    log("%.3f ms per call, %.2f G hashes/s, %.1f%% of INT32 VALU peak"
+        % (np.median(ev), comp / np.median(ev) / 1e6, 100 * achieved / PEAK_INT32_TOPS))
+    result = {
+        "metric": "verified hash-chain steps/sec on 1 GPU; %peak INT32 VALU",
+        "value": comp / (ms / 1e3), "unit": "hashes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "hash-chain segments: %d x %d hashes" % (n, T),
+                   "segments": n, "hashes_per_segment": T},
+        "roofline": {"kernel": "k_poh_verify", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_INT32_TOPS, "unit": "T int32 lane-instr/s",
+                     "frac": achieved / PEAK_INT32_TOPS, "traffic": None,
+                     "per_launch": "%d compressions x %d VALU instr" % (comp, I_REF),
+                     "avg_ms": float(np.median(ev))},
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        sample = min(n, 1 << 14)
+        t = time.perf_counter()
+        oracle.poh_verify(w.start[:sample], w.end[:sample], w.steps[:sample], threads)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": sample * T / dt, "unit": "hashes/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": "the first %d of %d segments (%.2f s)" % (sample, n, dt)}
+    return result
+
+
 def bench_sweep_table(args) -> dict:
     """The throughput sweep's grid: n = 1..16M transactions, resident midstates
     against keys derived in the step, the per-transaction derivation ablation,
@@ -506,11 +559,14 @@ def main() -> int:
                     help="derive every identity's key in the step, or use resident midstates")
     ap.add_argument("--mode", choices=["binned", "binned-persistent", "ordered"], default="binned")
     ap.add_argument("--workload", choices=["sweep", "batching", "serving", "sweep-table",
-                                           "attest"],
+                                           "attest", "poh"],
                     default="sweep",
                     help="sweep: the throughput sweep (default); batching: 256 uneven blocks; "
                          "serving: Poisson requests through the serving engine; "
-                         "attest: paper-form attestations with payload binding")
+                         "attest: paper-form attestations with payload binding; "
+                         "poh: hash-chain segment verification")
+    ap.add_argument("--poh-segments", type=int, default=1 << 18)
+    ap.add_argument("--poh-steps", type=int, default=1024)
     ap.add_argument("--pool", type=int, default=4 << 20, help="serving: transactions in the pool")
     ap.add_argument("--n-id-serving", type=int, default=4 << 20, help="serving: identities")
     ap.add_argument("--arena-gib", type=int, default=8, help="serving: device arena")
@@ -539,6 +595,9 @@ def main() -> int:
         return 0
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return 0
+    if args.workload == "poh":
+        print(json.dumps(bench_poh(args)), flush=True)
         return 0
     if args.workload == "attest":
         print(json.dumps(bench_attest(args)), flush=True)

@@ -331,6 +331,24 @@ ACE_API int ace_profile_enable(int on);
 ACE_API int ace_profile_read(ace_profile *out, int reset);
 
 /*
+ * ace_poh_verify -- segments of the SHA-256 hash chain that the consensus
+ * section uses as its clock (H_{i+1} = SHA-256(H_i), the 32 digest bytes
+ * hashed as a 32-byte message).  Segment i is valid iff applying SHA-256
+ * steps_i times to start[i] gives end[i] (full 32-byte compare), where
+ * steps_i = d_steps[i], or `steps` for every segment when d_steps is NULL.
+ *   d_start, d_end  [n_segments][32] bytes, 4-byte aligned.  For the
+ *                   checkpoints C[0..n] of one chain pass d_start = C and
+ *                   d_end = C + 32.
+ *   d_bitmask_out   [ceil(n_segments / 32)] words, fully written.
+ *   d_count_out     one uint64: number of valid segments (0 for n == 0).
+ * Segments run in parallel, each one's hashes in sequence, so a launch
+ * needs many segments (hundreds of thousands) to fill the device.
+ */
+ACE_API int ace_poh_verify(const uint8_t *d_start, const uint8_t *d_end, const uint32_t *d_steps,
+                           uint32_t steps, uint64_t n_segments, uint32_t *d_bitmask_out,
+                           uint64_t *d_count_out, void *stream);
+
+/*
  * ace_valu_rate -- measurement aid, not a step of the method: the INT32 VALU
  * issue rate the verify kernels are priced against.  Launches wgs_per_cu
  * workgroups of 256 lanes per CU, each lane running `iters` x 192 dependent

@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.ace_derive_keys_multi.argtypes = [vp, u32, ctypes.POINTER(ace_hkdf_stream), u32, vp, vp,
                                           vp]
     lib.ace_derive_keys_multi.restype = ctypes.c_int
+    lib.ace_poh_verify.argtypes = [vp, vp, vp, u32, ctypes.c_uint64, vp, vp, vp]
+    lib.ace_poh_verify.restype = ctypes.c_int
     lib.ace_valu_rate.argtypes = [u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.ace_valu_rate.restype = ctypes.c_int
     lib.ace_verify_attestations.argtypes = lib.ace_verify_batch.argtypes
@@ -279,6 +281,18 @@ def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
                         stream=None) -> torch.Tensor:
     """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
     return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream)
+
+
+def poh_verify(start: torch.Tensor, end: torch.Tensor, steps, bitmask: torch.Tensor,
+               count: torch.Tensor, stream=None) -> None:
+    """ace_poh_verify: `steps` is an int (every segment) or a uint32 tensor [n]."""
+    n = int(start.shape[0])
+    if isinstance(steps, torch.Tensor):
+        d_steps, uni = _ptr(steps), 0
+    else:
+        d_steps, uni = None, int(steps)
+    _check(load().ace_poh_verify(_ptr(start), _ptr(end), d_steps, uni, n, _ptr(bitmask),
+                                 _ptr(count), _stream(stream)))
 
 
 def valu_rate(iters: int = 20000, wgs_per_cu: int = 8, stream=None) -> float:

@@ -560,6 +560,32 @@ ACE_API int ace_derive_keys_multi(const uint8_t *d_rev, uint32_t n_id,
     return ACE_OK;
 }
 
+ACE_API int ace_poh_verify(const uint8_t *d_start, const uint8_t *d_end, const uint32_t *d_steps,
+                           uint32_t steps, uint64_t n_segments, uint32_t *d_bitmask_out,
+                           uint64_t *d_count_out, void *stream)
+{
+    clear_error();
+    if (!d_count_out) return fail(ACE_ERR_INVALID_ARG, "d_count_out is NULL");
+    if (!aligned(d_count_out, 8)) return fail(ACE_ERR_INVALID_ARG, "d_count_out not 8-byte aligned");
+    if (n_segments > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "n_segments too large");
+    if (n_segments) {
+        if (!d_start || !d_end || !d_bitmask_out)
+            return fail(ACE_ERR_INVALID_ARG, "NULL array with n_segments > 0");
+        if (!aligned(d_start, 4) || !aligned(d_end, 4) || !aligned(d_bitmask_out, 4) ||
+            (d_steps && !aligned(d_steps, 4)))
+            return fail(ACE_ERR_INVALID_ARG, "misaligned device array");
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d_count_out);
+    hipLaunchKernelGGL(k_poh_zero, dim3(1), dim3(1), 0, s, cnt);
+    int rc = launch_status("k_poh_zero launch");
+    if (rc || !n_segments) return rc;
+    const unsigned g = (unsigned)((n_segments + kWG - 1) / kWG);
+    hipLaunchKernelGGL(k_poh_verify, dim3(g), dim3(kWG), 0, s, d_start, d_end, d_steps, steps,
+                       n_segments, d_bitmask_out, cnt);
+    return launch_status("k_poh_verify launch");
+}
+
 ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,
                                          uint32_t n_blocks, uint32_t flags)
 {

@@ -444,13 +444,14 @@ class ChainWorkload:
 
 def poh_segments(n: int = 65536, steps=4096, seed: int = SEED_BASE + 7, chained: bool = False,
                  n_invalid: int | None = None, p_invalid: float = 0.005,
-                 nthreads=None) -> ChainWorkload:
+                 step_errors: bool = True, nthreads=None) -> ChainWorkload:
     """Segments of a SHA-256 hash chain (the clock of the consensus section):
     a checkpoint every `steps` hashes (an int, or one count per segment).
     chained=True draws one chain H_0 .. and cuts it at the checkpoints (end[i]
     == start[i+1]); otherwise every segment starts from its own random value,
     which has the same per-segment work and can be generated in parallel.
-    Invalid segments: a bit of the end checkpoint flipped, or one step too few."""
+    Invalid segments: a bit of the end checkpoint flipped, or (step_errors) a
+    claimed step count one more than the hashes that lead to the end."""
     ss = np.random.SeedSequence(seed)
     r_start, r_bad, r_kind, r_bit = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(4)]
     st = (np.full(n, int(steps), np.uint32) if np.isscalar(steps)
@@ -471,7 +472,7 @@ def poh_segments(n: int = 65536, steps=4096, seed: int = SEED_BASE + 7, chained:
     if n_invalid is None:
         n_invalid = int(np.floor(p_invalid * n + 0.5))
     bad = r_bad.choice(n, size=n_invalid, replace=False) if n_invalid else np.zeros(0, np.int64)
-    kind = r_kind.integers(0, 2, size=n_invalid)
+    kind = r_kind.integers(0, 2 if step_errors else 1, size=n_invalid)
     kind = np.where(st[bad] == 0, 0, kind)      # a zero-step segment cannot lose a step
     bit = r_bit.integers(0, 256, size=n_invalid)
     end = end.copy()

@@ -145,6 +145,20 @@ def test_derive_multi_argument_errors(lib):
     assert lib.ace_derive_keys_multi(None, 4, arr, 0, 0x2000, None, None) == ace.ACE_OK
 
 
+def test_poh_argument_errors(lib):
+    from paper_2603_10242_amd import ace
+    E = ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_poh_verify(0x1000, 0x2000, None, 5, 10, 0x3000, None, None) == E
+    assert lib.ace_poh_verify(0x1000, 0x2000, None, 5, 10, 0x3000, 0x4004, None) == E
+    assert lib.ace_poh_verify(None, 0x2000, None, 5, 10, 0x3000, 0x4000, None) == E
+    assert lib.ace_poh_verify(0x1000, None, None, 5, 10, 0x3000, 0x4000, None) == E
+    assert lib.ace_poh_verify(0x1000, 0x2000, None, 5, 10, None, 0x4000, None) == E
+    assert lib.ace_poh_verify(0x1001, 0x2000, None, 5, 10, 0x3000, 0x4000, None) == E
+    assert lib.ace_poh_verify(0x1000, 0x2000, 0x5002, 5, 10, 0x3000, 0x4000, None) == E
+    assert lib.ace_poh_verify(0x1000, 0x2000, None, 5, 2**33, 0x3000, 0x4000,
+                              None) == ace.ACE_ERR_RANGE
+
+
 def test_workspace_size_layout(lib):
     from paper_2603_10242_amd import ace
     ks, keep = _keyset(ace)
