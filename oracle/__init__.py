@@ -19,4 +19,5 @@ from .oracle import (  # noqa: F401
     verify_batch_rev,
     verify_attest,
     poh_verify,
+    merkle_roots,
 )

@@ -20,6 +20,13 @@
  *     message under the identity's key and compare with the credential;
  *     an identity outside the registry is rejected (Alg. 2, identity
  *     existence check).
+ *   - Paper-form attestation: Def. 3.1 (obj_hash, domain, credential) with
+ *     Alg. 2's payload binding.
+ *   - Hash-chain segments: the consensus section's clock, H_{i+1} =
+ *     SHA-256(H_i).
+ *   - Merkle roots of the block header (App. C, Table "ACE block header
+ *     fields"); the paper fixes no leaf or odd-node rule, so the reading
+ *     taken is written at oracle_merkle_root.
  *
  * Pins (none of them this file): hashlib / hmac / the openssl CLI on seeded
  * inputs, exact integer closed forms for the constants, brute force over
@@ -407,4 +414,43 @@ void oracle_poh_verify(const uint8_t *start, const uint8_t *end, const uint32_t 
     t.seg_start = start; t.seg_end = end; t.seg_steps = steps;
     t.bitmask = bitmask_out;
     run_split(&t, (size_t)n, nthreads, 32, count_out);
+}
+
+/* Merkle root of the n leaves data[off[i] .. off[i+1]) (the block header's
+ * transaction and attestation roots): leaf node = SHA-256(leaf bytes), parent
+ * = SHA-256(left || right); when a level has an odd count its last node moves
+ * up unchanged; no leaves gives SHA-256 of the empty string.  A leaf with
+ * off[i+1] < off[i] is hashed as the empty string.  Returns 0, or -1 when
+ * memory runs out. */
+int oracle_merkle_root(const uint8_t *data, const uint64_t *off, uint64_t n, uint8_t root[32])
+{
+    static const uint8_t none = 0;
+    if (n == 0) {
+        oracle_sha256(&none, 0, root);
+        return 0;
+    }
+    uint8_t *lvl = (uint8_t *)malloc((size_t)(32 * n));
+    if (!lvl) return -1;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t a = off[i], b = off[i + 1];
+        oracle_sha256(b >= a ? data + a : &none, b >= a ? (size_t)(b - a) : 0, lvl + 32 * i);
+    }
+    uint64_t m = n;
+    while (m > 1) {
+        uint64_t k = 0;
+        for (uint64_t i = 0; i + 1 < m; i += 2, ++k) {
+            uint8_t pair[64];
+            memcpy(pair, lvl + 32 * i, 32);
+            memcpy(pair + 32, lvl + 32 * (i + 1), 32);
+            oracle_sha256(pair, 64, lvl + 32 * k);
+        }
+        if (m & 1) {
+            memmove(lvl + 32 * k, lvl + 32 * (m - 1), 32);
+            ++k;
+        }
+        m = k;
+    }
+    memcpy(root, lvl, 32);
+    free(lvl);
+    return 0;
 }

@@ -55,6 +55,8 @@ def _load():
                                         ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
     lib.oracle_verify_attest.argtypes = [_u8p, ctypes.c_uint32, _u8p, _u64p, _u32p, _u8p,
                                          ctypes.c_uint64, _u32p, _u64p, ctypes.c_int]
+    lib.oracle_merkle_root.argtypes = [_u8p, _u64p, ctypes.c_uint64, _u8p]
+    lib.oracle_merkle_root.restype = ctypes.c_int
     lib.oracle_poh_verify.argtypes = [_u8p, _u8p, _u32p, ctypes.c_uint64, _u32p, _u64p,
                                       ctypes.c_int]
     _lib = lib
@@ -205,3 +207,25 @@ def poh_verify(start: np.ndarray, end: np.ndarray, steps: np.ndarray,
         _load().oracle_poh_verify(_ptr(start, _u8p), _ptr(end, _u8p), _ptr(steps, _u32p), n,
                                   _ptr(mask, _u32p), ctypes.byref(cnt), nthreads)
     return mask[: (n + 31) // 32], int(cnt.value)
+
+
+def merkle_roots(data: np.ndarray, off: np.ndarray, tree_sizes) -> np.ndarray:
+    """Roots [n_trees][32] of consecutive trees: tree b holds the next
+    tree_sizes[b] leaves, leaf i being data[off[i] .. off[i+1])."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    sizes = np.asarray(tree_sizes, dtype=np.int64)
+    assert off.shape[0] == int(sizes.sum()) + 1
+    d_arg = data if data.size else np.zeros(1, np.uint8)
+    roots = np.zeros((sizes.shape[0], 32), np.uint8)
+    lib = _load()
+    first = 0
+    for b, n in enumerate(sizes):
+        sub = off[first:first + n + 1] if n else off[first:first + 1]
+        out = (ctypes.c_uint8 * 32)()
+        if lib.oracle_merkle_root(_ptr(d_arg, _u8p), _ptr(np.ascontiguousarray(sub), _u64p),
+                                  int(n), out) != 0:
+            raise MemoryError("oracle_merkle_root")
+        roots[b] = np.frombuffer(bytes(out), np.uint8)
+        first += int(n)
+    return roots

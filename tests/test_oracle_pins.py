@@ -436,3 +436,63 @@ def test_poh_segments_match_truth_and_openssl():
     assert (mask == w.truth_bitmask()).all()
     # both corruption kinds occurred; one step too few is rejected like a flipped bit
     assert set(map(int, w.meta["bad_kind"])) == {0, 1}
+
+
+# ---------------------------------------------------------------- Merkle roots
+def _mth(leaves):
+    """Merkle tree hash written the other way round: split at the largest power
+    of two below n (the left-complete shape of RFC 6962, without its prefix
+    bytes), leaf node = SHA-256(leaf)."""
+    n = len(leaves)
+    if n == 0:
+        return hashlib.sha256(b"").digest()
+    if n == 1:
+        return hashlib.sha256(leaves[0]).digest()
+    k = 1
+    while 2 * k < n:
+        k *= 2
+    return hashlib.sha256(_mth(leaves[:k]) + _mth(leaves[k:])).digest()
+
+
+def test_merkle_roots_against_recursive_split():
+    """The level-by-level form with odd nodes moving up equals the recursive
+    split form, for every tree size 0..70 and leaves of 0..200 bytes."""
+    r = _rng(51)
+    sizes = np.arange(0, 71)
+    lens = r.integers(0, 201, size=int(sizes.sum()))
+    off = np.zeros(lens.size + 1, np.uint64)
+    np.cumsum(lens, out=off[1:])
+    data = r.integers(0, 256, size=int(off[-1]), dtype=np.uint8)
+    roots = oracle.merkle_roots(data, off, sizes)
+    first = 0
+    for b, n in enumerate(sizes):
+        leaves = [data[int(off[i]):int(off[i + 1])].tobytes() for i in range(first, first + n)]
+        assert roots[b].tobytes() == _mth(leaves), n
+        first += n
+
+
+def test_merkle_root_is_sensitive_to_every_leaf_bit_and_order():
+    r = _rng(52)
+    leaves = [_bytes(r, int(r.integers(1, 90))) for _ in range(13)]
+    off = np.zeros(14, np.uint64)
+    np.cumsum([len(x) for x in leaves], out=off[1:])
+    base = oracle.merkle_roots(np.frombuffer(b"".join(leaves), np.uint8), off, [13])[0]
+    seen = {base.tobytes()}
+    for i in range(13):
+        for bit in range(0, 8 * len(leaves[i]), 7):
+            mod = [bytearray(x) for x in leaves]
+            mod[i][bit // 8] ^= 1 << (bit % 8)
+            root = oracle.merkle_roots(np.frombuffer(b"".join(mod), np.uint8), off, [13])[0]
+            assert root.tobytes() not in seen
+            seen.add(root.tobytes())
+    swapped = leaves[:]
+    swapped[3], swapped[4] = swapped[4], swapped[3]
+    off2 = np.zeros(14, np.uint64)
+    np.cumsum([len(x) for x in swapped], out=off2[1:])
+    assert oracle.merkle_roots(np.frombuffer(b"".join(swapped), np.uint8), off2, [13])[0] \
+        .tobytes() != base.tobytes()
+    # decreasing offsets: the leaf is hashed as the empty string
+    off3 = np.array([0, 5, 2, 9], np.uint64)
+    data = np.frombuffer(_bytes(r, 9), np.uint8)
+    got = oracle.merkle_roots(data, off3, [3])[0].tobytes()
+    assert got == _mth([data[0:5].tobytes(), b"", data[2:9].tobytes()])
