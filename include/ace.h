@@ -331,6 +331,36 @@ ACE_API int ace_profile_enable(int on);
 ACE_API int ace_profile_read(ace_profile *out, int reset);
 
 /*
+ * Merkle roots of the block header's transaction and attestation lists
+ * (App. C, fields tx_merkle_root and attest_merkle_root; a validator
+ * recomputes the attestation root before voting, Alg. 4).  The paper fixes
+ * no leaf or odd-node rule; the one implemented: leaf node = SHA-256(leaf
+ * bytes), parent = SHA-256(left || right), at a level with an odd count the
+ * last node moves up unchanged (the left-complete shape of RFC 6962, without
+ * its prefix bytes), and a tree without leaves has root SHA-256("").  A leaf
+ * with off[i+1] < off[i] is hashed as the empty string.
+ */
+typedef struct {
+    const uint8_t *d_data;   /* leaves back to back; may be NULL only if n_leaves == 0    */
+    const uint64_t *d_off;   /* [n_leaves + 1] byte offsets into d_data (8-byte aligned) */
+    uint64_t n_leaves;
+    uint8_t *d_root_out;     /* 32 bytes, 4-byte aligned                                  */
+} ace_merkle_tree;
+
+/* Workspace bytes for these trees: 32 per leaf plus small tables (0 on bad arguments). */
+ACE_API size_t ace_merkle_workspace_size(const ace_merkle_tree *trees, uint32_t n_trees);
+
+/*
+ * ace_merkle_roots -- the roots of n_trees trees in one pass: every leaf of
+ * every tree hashed in parallel, then one launch per tree level over all
+ * trees.  h-side `trees` is read before the call returns; d_workspace is at
+ * least ace_merkle_workspace_size() bytes, 256-byte aligned.  Total leaves
+ * <= ACE_MAX_TX, n_trees < 2^24.
+ */
+ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, void *d_workspace,
+                             size_t ws_bytes, void *stream);
+
+/*
  * ace_poh_verify -- segments of the SHA-256 hash chain that the consensus
  * section uses as its clock (H_{i+1} = SHA-256(H_i), the 32 digest bytes
  * hashed as a 32-byte message).  Segment i is valid iff applying SHA-256

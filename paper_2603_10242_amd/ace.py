@@ -60,6 +60,11 @@ class ace_hkdf_stream(ctypes.Structure):
                 ("h_info", ctypes.c_void_p), ("info_len", ctypes.c_size_t)]
 
 
+class ace_merkle_tree(ctypes.Structure):
+    _fields_ = [("d_data", ctypes.c_void_p), ("d_off", ctypes.c_void_p),
+                ("n_leaves", ctypes.c_uint64), ("d_root_out", ctypes.c_void_p)]
+
+
 class ace_tuning(ctypes.Structure):
     _fields_ = [("binned_min_tx", ctypes.c_uint64), ("verify_wgs_per_cu", ctypes.c_uint32),
                 ("aux_wgs_per_cu", ctypes.c_uint32), ("auto_persistent", ctypes.c_uint32)]
@@ -96,6 +101,10 @@ def load(path: str = LIB_PATH):
     lib.ace_derive_keys_multi.argtypes = [vp, u32, ctypes.POINTER(ace_hkdf_stream), u32, vp, vp,
                                           vp]
     lib.ace_derive_keys_multi.restype = ctypes.c_int
+    lib.ace_merkle_workspace_size.argtypes = [ctypes.POINTER(ace_merkle_tree), u32]
+    lib.ace_merkle_workspace_size.restype = sz
+    lib.ace_merkle_roots.argtypes = [ctypes.POINTER(ace_merkle_tree), u32, vp, sz, vp]
+    lib.ace_merkle_roots.restype = ctypes.c_int
     lib.ace_poh_verify.argtypes = [vp, vp, vp, u32, ctypes.c_uint64, vp, vp, vp]
     lib.ace_poh_verify.restype = ctypes.c_int
     lib.ace_valu_rate.argtypes = [u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]
@@ -281,6 +290,24 @@ def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
                         stream=None) -> torch.Tensor:
     """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
     return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream)
+
+
+def merkle_roots(trees: Sequence[tuple[torch.Tensor, torch.Tensor, int, torch.Tensor]],
+                 ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """ace_merkle_roots over (data, off, n_leaves, root_out[32]) device tensors;
+    returns the workspace used."""
+    arr = (ace_merkle_tree * max(1, len(trees)))()
+    for i, (data, off, n, root) in enumerate(trees):
+        arr[i] = ace_merkle_tree(_ptr(data) if n else None, _ptr(off) if n else None, int(n),
+                                 _ptr(root))
+    lib = load()
+    need = int(lib.ace_merkle_workspace_size(arr, len(trees)))
+    if need == 0 and len(trees):
+        _check(lib.ace_merkle_roots(arr, len(trees), None, 0, None))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need)
+    _check(lib.ace_merkle_roots(arr, len(trees), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
 
 
 def poh_verify(start: torch.Tensor, end: torch.Tensor, steps, bitmask: torch.Tensor,

@@ -17,6 +17,7 @@
 // The kernels are compiled in this translation unit.
 #include "ace_kernels.hip"
 #include "valu_rate.hip"
+#include "merkle_kernels.hip"
 
 using namespace ace;
 
@@ -584,6 +585,116 @@ ACE_API int ace_poh_verify(const uint8_t *d_start, const uint8_t *d_end, const u
     hipLaunchKernelGGL(k_poh_verify, dim3(g), dim3(kWG), 0, s, d_start, d_end, d_steps, steps,
                        n_segments, d_bitmask_out, cnt);
     return launch_status("k_poh_verify launch");
+}
+
+}  // extern "C"
+
+namespace {
+
+struct MerklePlan {
+    uint64_t total;    // leaves of all trees
+    uint32_t levels;   // reductions of the largest tree
+    size_t off_table, off_nodes, off_prefix, bytes;
+};
+
+int merkle_plan(const ace_merkle_tree *trees, uint32_t n_trees, MerklePlan &p)
+{
+    if (n_trees && !trees) return fail(ACE_ERR_INVALID_ARG, "trees is NULL");
+    if (n_trees >= (1u << 24)) return fail(ACE_ERR_RANGE, "n_trees %u >= 2^24", n_trees);
+    p.total = 0;
+    p.levels = 0;
+    for (uint32_t b = 0; b < n_trees; ++b) {
+        const ace_merkle_tree &t = trees[b];
+        if (!t.d_root_out) return fail(ACE_ERR_INVALID_ARG, "tree %u: d_root_out is NULL", b);
+        if (!aligned(t.d_root_out, 4)) return fail(ACE_ERR_INVALID_ARG, "tree %u: d_root_out not 4-byte aligned", b);
+        if (t.n_leaves) {
+            if (!t.d_data || !t.d_off) return fail(ACE_ERR_INVALID_ARG, "tree %u: NULL array with n_leaves > 0", b);
+            if (!aligned(t.d_off, 8)) return fail(ACE_ERR_INVALID_ARG, "tree %u: d_off not 8-byte aligned", b);
+        }
+        if (t.n_leaves > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "tree %u: n_leaves too large", b);
+        p.total += t.n_leaves;
+        if (p.total > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "total leaves exceed ACE_MAX_TX");
+        uint32_t lv = 0;
+        while (lv < 63 && (1ull << lv) < t.n_leaves) ++lv;
+        p.levels = std::max(p.levels, lv);
+    }
+    size_t o = 0;
+    p.off_table = o;  o = align_up(o + sizeof(MerkleDesc) * (size_t)n_trees, 256);
+    p.off_nodes = o;  o = align_up(o + 32ull * p.total, 256);
+    p.off_prefix = o; o = align_up(o + 8ull * p.levels * (n_trees + 1ull), 256);
+    p.bytes = std::max<size_t>(o, 256);
+    return ACE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ACE_API size_t ace_merkle_workspace_size(const ace_merkle_tree *trees, uint32_t n_trees)
+{
+    MerklePlan p;
+    if (merkle_plan(trees, n_trees, p) != ACE_OK) return 0;
+    return p.bytes;
+}
+
+ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, void *d_workspace,
+                             size_t ws_bytes, void *stream)
+{
+    clear_error();
+    MerklePlan p;
+    int rc = merkle_plan(trees, n_trees, p);
+    if (rc) return rc;
+    if (n_trees == 0) return ACE_OK;
+    if (!d_workspace) return fail(ACE_ERR_INVALID_ARG, "d_workspace is NULL");
+    if (!aligned(d_workspace, 256)) return fail(ACE_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
+    if (ws_bytes < p.bytes) return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    MerkleDesc *table = reinterpret_cast<MerkleDesc *>(ws + p.off_table);
+    uint32_t *nodes = reinterpret_cast<uint32_t *>(ws + p.off_nodes);
+    unsigned long long *P = reinterpret_cast<unsigned long long *>(ws + p.off_prefix);
+
+    MerkleChunk chunk;
+    memset(&chunk, 0, sizeof chunk);
+    uint64_t leaf0 = 0;
+    for (uint32_t b = 0; b < n_trees; ++b) {
+        MerkleDesc &d = chunk.d[chunk.count++];
+        d.data = trees[b].d_data;
+        d.off = trees[b].d_off;
+        d.n = trees[b].n_leaves;
+        d.root = trees[b].d_root_out;
+        d.leaf0 = leaf0;
+        leaf0 += d.n;
+        if (chunk.count == kMerkleChunk || b + 1 == n_trees) {
+            hipLaunchKernelGGL(k_merkle_put, dim3(1), dim3(kMerkleChunk), 0, s, table, chunk);
+            if ((rc = launch_status("k_merkle_put launch"))) return rc;
+            chunk.first = b + 1;
+            chunk.count = 0;
+        }
+    }
+    if (p.total) {
+        hipLaunchKernelGGL(k_merkle_leaves, dim3((unsigned)((p.total + kWG - 1) / kWG)), dim3(kWG), 0, s,
+                           table, n_trees, p.total, nodes);
+        if ((rc = launch_status("k_merkle_leaves launch"))) return rc;
+    }
+    if (p.levels) {
+        hipLaunchKernelGGL(k_merkle_plan, dim3(1), dim3(kPlanThreads), 0, s, table, n_trees, p.levels, P);
+        if ((rc = launch_status("k_merkle_plan launch"))) return rc;
+    }
+    for (uint32_t k = 0; k < p.levels; ++k) {
+        // this level's pairs over all trees, as the plan kernel counts them
+        uint64_t pairs = 0;
+        for (uint32_t b = 0; b < n_trees; ++b) {
+            const uint64_t n = trees[b].n_leaves;
+            pairs += ((n + (1ull << k) - 1) >> k) >> 1;
+        }
+        if (!pairs) continue;
+        hipLaunchKernelGGL(k_merkle_level, dim3((unsigned)((pairs + kWG - 1) / kWG)), dim3(kWG), 0, s, table,
+                           n_trees, k, P + (uint64_t)k * (n_trees + 1ull), nodes);
+        if ((rc = launch_status("k_merkle_level launch"))) return rc;
+    }
+    hipLaunchKernelGGL(k_merkle_out, dim3((n_trees + kWG - 1) / kWG), dim3(kWG), 0, s, table, n_trees, nodes);
+    return launch_status("k_merkle_out launch");
 }
 
 ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,

@@ -1,0 +1,236 @@
+// merkle_kernels.hip -- Merkle roots of the block header's transaction and
+// attestation lists (App. C, block header fields tx_merkle_root and
+// attest_merkle_root; a validator recomputes the attestation root, Alg. 4).
+//
+// Reading (the paper fixes neither): leaf node = SHA-256(leaf bytes); parent
+// = SHA-256(left || right); at a level with an odd number of nodes the last
+// one moves up unchanged; a tree without leaves has the root SHA-256("").
+//
+// Layout: node j of level k of a tree whose leaves start at global leaf
+// index leaf0 lives in slot leaf0 + j * 2^k of one node array (8 native
+// words per slot).  A parent overwrites its left child's slot, so levels are
+// reduced in place, and an unpaired last node is already where the next
+// level expects it.
+//
+//   k_merkle_leaves  one leaf per lane: SHA-256 of its bytes into its slot.
+//   k_merkle_plan    per level, exclusive prefix of each tree's pair count.
+//   k_merkle_level   one parent per lane at level k -> k + 1 (two blocks:
+//                    the 64 child bytes, then the constant padding block).
+//   k_merkle_out     roots to the callers' 32-byte outputs.
+
+namespace ace {
+
+struct MerkleDesc {
+    const uint8_t *data;
+    const uint64_t *off;
+    uint64_t n;      // leaves
+    uint8_t *root;   // 32-byte output
+    uint64_t leaf0;  // global index of the first leaf
+};
+
+constexpr uint32_t kMerkleChunk = 64;
+struct MerkleChunk {
+    MerkleDesc d[kMerkleChunk];
+    uint32_t first;
+    uint32_t count;
+};
+
+__global__ void k_merkle_put(MerkleDesc *table, MerkleChunk c)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < c.count) table[c.first + t] = c.d[t];
+}
+
+// Last tree whose first leaf is <= g (trees with no leaves are skipped by
+// taking the last of equal starts).
+__device__ __forceinline__ uint32_t merkle_tree_of(const MerkleDesc *table, uint32_t n_trees,
+                                                   uint64_t g)
+{
+    uint32_t lo = 0, hi = n_trees;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (table[mid].leaf0 <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// SHA-256 of L bytes at p into S (from the initial value).  Every dword
+// address is clamped to one that holds message bytes (for L == 0 none is
+// read), so nothing outside the leaf's bytes is touched.
+__device__ __forceinline__ void sha256_bytes(bool live, const uint8_t *p, uint64_t L, State &S)
+{
+    S = initial_state();
+    const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+    const uint32_t sh = (uint32_t)addr & 3u;
+    const uint32_t sel = 0x00010203u + sh * 0x01010101u;
+    const uint64_t lim = (uint64_t)sh + L;
+    const uint64_t last = lim ? ((lim - 1) >> 2) : 0;
+    const uint32_t *A0 = reinterpret_cast<const uint32_t *>(addr - sh);
+    const uint64_t bits = L << 3;
+    for (uint32_t b = 0;; ++b) {
+        const bool run = live && b < nb;
+        if (__ballot(run) == 0) break;
+        if (run) {
+            uint32_t D[17], W[16];
+#pragma unroll
+            for (int k = 0; k < 17; ++k) {
+                const uint64_t idx = 16ull * b + k;
+                D[k] = lim ? A0[idx < last ? idx : last] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+            const int64_t rb = (int64_t)L - 64 * (int64_t)b;
+            if (rb < 64) {
+                const int32_t r0 = (int32_t)rb;
+                const int32_t jf = r0 >> 2;
+                const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
+                const uint32_t keep = ~(0xFFFFFFFFu >> c8);
+                const uint32_t pad = 0x80000000u >> c8;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t part = (W[j] & keep) | pad;
+                    W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
+                }
+                if (b + 1 == nb) {
+                    W[14] = (uint32_t)(bits >> 32);
+                    W[15] = (uint32_t)bits;
+                }
+            }
+            compress_block(S, W);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kWG) k_merkle_leaves(const MerkleDesc *__restrict__ table,
+                                                       uint32_t n_trees, uint64_t n_leaves,
+                                                       uint32_t *__restrict__ nodes)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool live = g < n_leaves;
+    const uint8_t *p = nullptr;
+    uint64_t L = 0;
+    if (live) {
+        const MerkleDesc d = table[merkle_tree_of(table, n_trees, g)];
+        const uint64_t i = g - d.leaf0;
+        const uint64_t a = d.off[i], e = d.off[i + 1];
+        p = d.data + a;
+        L = e >= a ? e - a : 0;  // decreasing offsets: the empty leaf
+    }
+    State S;
+    sha256_bytes(live, p, L, S);
+    if (live) {
+        uint32_t *q = nodes + 8ull * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = S.h[k];
+    }
+}
+
+// P[k * (n_trees + 1) + b] = pairs at level k of trees before b; the last
+// entry of each row is the level's total.  One workgroup of kPlanThreads.
+constexpr uint32_t kPlanThreads = 1024;
+__global__ void __launch_bounds__(kPlanThreads) k_merkle_plan(const MerkleDesc *__restrict__ table,
+                                                              uint32_t n_trees, uint32_t levels,
+                                                              unsigned long long *__restrict__ P)
+{
+    __shared__ unsigned long long part[kPlanThreads];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t k = 0; k < levels; ++k) {
+        unsigned long long *row = P + (uint64_t)k * (n_trees + 1);
+        unsigned long long running = 0;
+        for (uint32_t c = 0; c < n_trees; c += kPlanThreads) {
+            const uint32_t b = c + t;
+            unsigned long long v = 0;
+            if (b < n_trees) {
+                const uint64_t n = table[b].n;
+                const uint64_t m = k >= 63 ? (n ? 1 : 0) : (n + (1ull << k) - 1) >> k;
+                v = m >> 1;
+            }
+            part[t] = v;
+            __syncthreads();
+            // Hillis-Steele inclusive scan
+            for (uint32_t s = 1; s < kPlanThreads; s <<= 1) {
+                const unsigned long long add = t >= s ? part[t - s] : 0ull;
+                __syncthreads();
+                part[t] += add;
+                __syncthreads();
+            }
+            if (b < n_trees) row[b] = running + part[t] - v;
+            running += part[kPlanThreads - 1];
+            __syncthreads();
+        }
+        if (t == 0) row[n_trees] = running;
+    }
+}
+
+__global__ void __launch_bounds__(kWG) k_merkle_level(const MerkleDesc *__restrict__ table,
+                                                      uint32_t n_trees, uint32_t k,
+                                                      const unsigned long long *__restrict__ Pk,
+                                                      uint32_t *__restrict__ nodes)
+{
+    const uint64_t q = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool live = q < Pk[n_trees];
+    uint32_t W[16];
+    uint64_t left = 0;
+    if (live) {
+        // last tree whose prefix is <= q
+        uint32_t lo = 0, hi = n_trees;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (Pk[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t p = q - Pk[lo];
+        left = table[lo].leaf0 + ((2 * p) << k);
+        const uint64_t right = left + (1ull << k);
+        const uint32_t *a = nodes + 8ull * left;
+        const uint32_t *b = nodes + 8ull * right;
+        const U4 a0 = load16(a), a1 = load16(a + 4), b0 = load16(b), b1 = load16(b + 4);
+        W[0] = a0.x; W[1] = a0.y; W[2] = a0.z; W[3] = a0.w;
+        W[4] = a1.x; W[5] = a1.y; W[6] = a1.z; W[7] = a1.w;
+        W[8] = b0.x; W[9] = b0.y; W[10] = b0.z; W[11] = b0.w;
+        W[12] = b1.x; W[13] = b1.y; W[14] = b1.z; W[15] = b1.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) W[j] = 0;
+    }
+    if (__ballot(live) == 0) return;
+    State S = initial_state();
+    compress_block(S, W);
+    // the 64-byte message's padding block: 0x80, zeros, bit length 512
+    W[0] = 0x80000000u;
+#pragma unroll
+    for (int j = 1; j < 15; ++j) W[j] = 0u;
+    W[15] = 512u;
+    compress_block(S, W);
+    if (live) {
+        uint32_t *o = nodes + 8ull * left;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = S.h[j];
+    }
+}
+
+__global__ void __launch_bounds__(kWG) k_merkle_out(const MerkleDesc *__restrict__ table,
+                                                    uint32_t n_trees,
+                                                    const uint32_t *__restrict__ nodes)
+{
+    const uint32_t b = blockIdx.x * kWG + threadIdx.x;
+    const bool live = b < n_trees;
+    MerkleDesc d{};
+    if (live) d = table[b];
+    // SHA-256 of the empty string for a tree without leaves
+    State S;
+    sha256_bytes(live && d.n == 0, nullptr, 0, S);
+    if (!live) return;
+    if (d.n) {
+        const uint32_t *q = nodes + 8ull * d.leaf0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) S.h[j] = q[j];
+    }
+    uint32_t *o = reinterpret_cast<uint32_t *>(d.root);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = bswap32(S.h[j]);
+}
+
+}  // namespace ace

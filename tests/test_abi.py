@@ -159,6 +159,31 @@ def test_poh_argument_errors(lib):
                               None) == ace.ACE_ERR_RANGE
 
 
+def test_merkle_argument_errors_and_workspace(lib):
+    from paper_2603_10242_amd import ace
+    E = ace.ACE_ERR_INVALID_ARG
+    arr = (ace.ace_merkle_tree * 3)()
+    arr[0] = ace.ace_merkle_tree(0x1000, 0x2000, 10, 0x3000)
+    arr[1] = ace.ace_merkle_tree(None, None, 0, 0x3020)
+    arr[2] = ace.ace_merkle_tree(0x1000, 0x2000, 1000, 0x3040)
+    # 32 bytes per leaf, the descriptor table and per-level prefixes (10 levels)
+    need = lib.ace_merkle_workspace_size(arr, 3)
+    assert need >= 32 * 1010 + 40 * 3 + 8 * 10 * 4 and need % 256 == 0
+    assert lib.ace_merkle_roots(arr, 3, None, 0, None) == E
+    assert lib.ace_merkle_roots(arr, 3, 0x100000, need - 1, None) == ace.ACE_ERR_NO_MEMORY
+    assert lib.ace_merkle_roots(arr, 3, 0x100010, need, None) == E          # misaligned workspace
+    arr[1] = ace.ace_merkle_tree(None, None, 0, None)                         # no root output
+    assert lib.ace_merkle_roots(arr, 3, 0x100000, need, None) == E
+    arr[1] = ace.ace_merkle_tree(None, None, 0, 0x3022)                       # misaligned root
+    assert lib.ace_merkle_roots(arr, 3, 0x100000, need, None) == E
+    arr[1] = ace.ace_merkle_tree(None, 0x2000, 5, 0x3020)                     # NULL data
+    assert lib.ace_merkle_roots(arr, 3, 0x100000, need, None) == E
+    arr[1] = ace.ace_merkle_tree(0x1000, 0x2004, 5, 0x3020)                   # misaligned offsets
+    assert lib.ace_merkle_roots(arr, 3, 0x100000, need, None) == E
+    assert lib.ace_merkle_workspace_size(None, 2) == 0
+    assert lib.ace_merkle_roots(arr, 0, None, 0, None) == ace.ACE_OK           # nothing to do
+
+
 def test_workspace_size_layout(lib):
     from paper_2603_10242_amd import ace
     ks, keep = _keyset(ace)
