@@ -79,7 +79,7 @@ def test_every_payload_length_0_to_1300(ace, mode):
     for g, lo in enumerate(range(0, L.size, 100)):
         hi = min(L.size, lo + 100)
         w = W.paper_attestations(n=hi - lo, n_id=64, lengths=L[lo:hi], id_dist="uniform",
-                                 n_invalid=10, seed=W.SEED_BASE + 100 + g)
+                                 n_invalid=(hi - lo) // 10, seed=W.SEED_BASE + 100 + g)
         lead = g % 4
         poff = w.poff + lead
         buf = np.concatenate([np.zeros(lead, np.uint8), w.payload])
