@@ -487,6 +487,60 @@ def bench_poh(args) -> dict:
     return result
 
 
+def bench_merkle(args) -> dict:
+    """Attestation Merkle roots of the batching workload's 256 blocks: one root
+    per block over its 72-byte attestation records."""
+    from paper_2603_10242_amd import workload as W
+    sizes = W.batching_block_sizes()
+    n = int(sizes.sum())
+    log("generating %d attestation records in %d blocks" % (n, sizes.size))
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([W.SEED_BASE + 8])))
+    data = rng.integers(0, 256, size=72 * n, dtype=np.uint8)
+    off = np.arange(n + 1, dtype=np.uint64) * 72
+    import torch
+    from paper_2603_10242_amd import ace
+    ace.load()
+    torch.cuda.set_device(0)
+    d_data = ace.to_device(data)
+    d_off = ace.to_device(off)
+    roots = torch.zeros((sizes.size, 32), dtype=torch.uint8, device="cuda")
+    trees, first = [], 0
+    for b, m in enumerate(sizes):
+        trees.append((d_data, d_off[first:first + int(m) + 1], int(m), roots[b]))
+        first += int(m)
+    ws = ace.merkle_roots(trees)
+    torch.cuda.synchronize()
+    check = [0, sizes.size // 2, sizes.size - 1]
+    firsts = np.concatenate([[0], np.cumsum(sizes)])
+    for b in check:
+        lo, hi = int(firsts[b]), int(firsts[b + 1])
+        want = W.client_merkle_root(data[72 * lo:72 * hi], off[lo:hi + 1] - off[lo])
+        if roots[b].cpu().numpy().tobytes() != want:
+            raise SystemExit("RESULT MISMATCH in block %d" % b)
+    log("roots of blocks %s equal the client's" % check)
+    ms, ev = time_calls(lambda: ace.merkle_roots(trees, ws), args.steps, args.warmup)
+    comp = 2 * n + 2 * int(np.maximum(sizes - 1, 0).sum())   # 72-byte leaves: 2 blocks each
+    achieved = comp * I_REF / (np.median(ev) / 1e3) / 1e12
+    log("%.3f ms per call (%d roots), %.1f%% of INT32 VALU peak"
+        % (np.median(ev), sizes.size, 100 * achieved / PEAK_INT32_TOPS))
+    return {
+        "metric": "attestation Merkle roots: leaves/sec on 1 GPU; %peak INT32 VALU",
+        "value": n / (ms / 1e3), "unit": "leaves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "Merkle roots of 256 blocks (%d attestation records of 72 B)" % n,
+                   "blocks": int(sizes.size), "leaves": n},
+        "roofline": {"kernel": "k_merkle_leaves + k_merkle_level", "bound": "alu",
+                     "achieved": achieved, "peak": PEAK_INT32_TOPS,
+                     "unit": "T int32 lane-instr/s", "frac": achieved / PEAK_INT32_TOPS,
+                     "traffic": None,
+                     "per_launch": "%d compressions x %d VALU instr" % (comp, I_REF),
+                     "avg_ms": float(np.median(ev))},
+        "p50_ms": float(np.percentile(ev, 50)), "p99_ms": float(np.percentile(ev, 99)),
+        "device": torch.cuda.get_device_name(0),
+    }
+
+
 def bench_sweep_table(args) -> dict:
     """The throughput sweep's grid: n = 1..16M transactions, resident midstates
     against keys derived in the step, the per-transaction derivation ablation,
@@ -559,12 +613,12 @@ def main() -> int:
                     help="derive every identity's key in the step, or use resident midstates")
     ap.add_argument("--mode", choices=["binned", "binned-persistent", "ordered"], default="binned")
     ap.add_argument("--workload", choices=["sweep", "batching", "serving", "sweep-table",
-                                           "attest", "poh"],
+                                           "attest", "poh", "merkle"],
                     default="sweep",
                     help="sweep: the throughput sweep (default); batching: 256 uneven blocks; "
                          "serving: Poisson requests through the serving engine; "
                          "attest: paper-form attestations with payload binding; "
-                         "poh: hash-chain segment verification")
+                         "poh: hash-chain segment verification; merkle: attestation roots")
     ap.add_argument("--poh-segments", type=int, default=1 << 18)
     ap.add_argument("--poh-steps", type=int, default=1024)
     ap.add_argument("--pool", type=int, default=4 << 20, help="serving: transactions in the pool")
@@ -595,6 +649,9 @@ def main() -> int:
         return 0
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return 0
+    if args.workload == "merkle":
+        print(json.dumps(bench_merkle(args)), flush=True)
         return 0
     if args.workload == "poh":
         print(json.dumps(bench_poh(args)), flush=True)

@@ -425,6 +425,24 @@ def paper_attestations(n: int = 2000, n_id: int = 1 << 16, seed: int = SEED_BASE
 
 
 # ------------------------------------------------------------------ hash-chain segments
+def client_merkle_root(data: np.ndarray, off: np.ndarray) -> bytes:
+    """Root over the leaves data[off[i] .. off[i+1]) as a client builds it:
+    leaf digests by OpenSSL, parents SHA-256(left || right) by hashlib, an
+    unpaired last node moved up, SHA-256("") for no leaves."""
+    import hashlib
+    n = off.shape[0] - 1
+    if n == 0:
+        return hashlib.sha256(b"").digest()
+    level = [bytes(x) for x in client_digest(data, off)]
+    while len(level) > 1:
+        nxt = [hashlib.sha256(level[i] + level[i + 1]).digest()
+               for i in range(0, len(level) - 1, 2)]
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    return level[0]
+
+
 @dataclasses.dataclass
 class ChainWorkload:
     name: str
