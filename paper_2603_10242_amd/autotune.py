@@ -120,8 +120,9 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
         log("persistent %2d WG/CU: %.3f ms (dispatcher-scheduled %.3f ms)" % (wpc, t, t_plain))
         if t < best[0]:
             best = (t, wpc)
-    # graphs always use the persistent kernel: keep its best shape even if the
-    # dispatcher-scheduled kernel wins in eager calls
+    # the persistent kernel's shape is kept even when the dispatcher-scheduled
+    # kernel wins, for callers that ask for it (ACE_PERSISTENT) and for the
+    # graph's grid-stride in-order kernel, which uses the same workgroups per CU
     best_wpc = best[1] if best[1] is not None else min(
         (m for m in meas if "persistent_wgs_per_cu" in m), key=lambda m: m["ms"])["persistent_wgs_per_cu"]
 
