@@ -95,7 +95,7 @@ struct ProfState {
     ~ProfState()
     {
         for (auto &c : calls)
-            for (auto &e : c.ev) hipEventDestroy(e);
+            for (auto &e : c.ev) (void)hipEventDestroy(e);
     }
 };
 thread_local ProfState g_prof;
@@ -110,13 +110,13 @@ ProfCall *prof_begin(hipStream_t s)
         g_prof.calls.push_back(c);
     }
     ProfCall *c = &g_prof.calls[g_prof.used++];
-    hipEventRecord(c->ev[0], s);
+    (void)hipEventRecord(c->ev[0], s);
     return c;
 }
 
 inline void prof_mark(ProfCall *c, int k, hipStream_t s)
 {
-    if (c) hipEventRecord(c->ev[k], s);
+    if (c) (void)hipEventRecord(c->ev[k], s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -433,12 +433,12 @@ void graph_free(ace_graph *g)
 {
     if (!g) return;
     for (auto &sl : g->slot) {
-        if (sl.exec) hipGraphExecDestroy(sl.exec);
-        if (sl.graph) hipGraphDestroy(sl.graph);
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.h_descs) hipHostFree(sl.h_descs);
+        if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+        if (sl.graph) (void)hipGraphDestroy(sl.graph);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.h_descs) (void)hipHostFree(sl.h_descs);
     }
-    if (g->capture) hipStreamDestroy(g->capture);
+    if (g->capture) (void)hipStreamDestroy(g->capture);
     delete g;
 }
 
@@ -473,7 +473,7 @@ ACE_API int ace_valu_rate(uint32_t iters, uint32_t wgs_per_cu, uint32_t *d_sink,
     float ms = 0.f;
     if (!rc) rc = check_hip(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
     for (hipEvent_t e : ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     const double lanes = (double)g * 256.0;
     const double instr = (double)iters * kValuStepsPerIter * kValuOpsPerStep;
@@ -867,7 +867,7 @@ ACE_API int ace_graph_create(const ace_keyset *keys, uint32_t max_blocks, uint64
         const size_t hb = align_up((size_t)max_blocks * sizeof(DevBlock), 256) + 256;
         if ((rc = check_hip(hipHostMalloc(&h, hb, hipHostMallocDefault), "hipHostMalloc")) ||
             (rc = check_hip(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate"))) {
-            if (h && !sl.h_descs) hipHostFree(h);
+            if (h && !sl.h_descs) (void)hipHostFree(h);
             graph_free(g);
             return rc;
         }
@@ -939,7 +939,7 @@ ACE_API int ace_graph_destroy(ace_graph *g)
     clear_error();
     if (!g) return ACE_OK;
     for (auto &sl : g->slot)
-        if (sl.used) hipEventSynchronize(sl.done);
+        if (sl.used) (void)hipEventSynchronize(sl.done);
     graph_free(g);
     return ACE_OK;
 }

@@ -158,9 +158,9 @@ class HipBackend : public Backend {
     ~HipBackend() override
     {
         for (auto s : streams_)
-            if (s) hipStreamDestroy(s);
+            if (s) (void)hipStreamDestroy(s);
         for (auto e : done_)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     }
     uint8_t *arena() override { return arena_; }
     int begin_slot(int) override { return check_hip(hipSetDevice(device_), "hipSetDevice"); }
@@ -541,11 +541,11 @@ static void stream_free(ace_stream *s)
     if (!s) return;
     for (auto &sl : s->slot) {
         if (!sl.result) continue;
-        if (s->staging_pinned) hipHostFree(sl.result);
+        if (s->staging_pinned) (void)hipHostFree(sl.result);
         else free(sl.result);
     }
     if (s->staging) {
-        if (s->staging_pinned) hipHostFree(s->staging);
+        if (s->staging_pinned) (void)hipHostFree(s->staging);
         else free(s->staging);
     }
     delete s;
