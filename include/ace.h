@@ -12,6 +12,13 @@
  * 40-byte case); an identity index outside the registry is rejected (the
  * identity existence check of Alg. 2).
  *
+ * Around it: the paper's own attestation form with the validator's payload
+ * binding (ace_verify_attestations), the keys of several HKDF streams
+ * (ace_derive_keys_multi), the block header's Merkle roots
+ * (ace_merkle_roots), segments of the hash-chain clock (ace_poh_verify), a
+ * captured-graph form of the batch call and a continuous-batching serving
+ * engine.
+ *
  * Conventions shared by every entry point:
  *   - d_* arguments are HIP device pointers owned by the caller; h_* are host
  *     pointers read before the call returns.  The library never frees or
@@ -317,6 +324,8 @@ ACE_API int ace_stream_create_host(ace_host_verify_fn fn, void *user, size_t are
  * kernel and the finalize pass.  ace_profile_read() waits for the recorded
  * events and returns the summed milliseconds of all profiled calls since the
  * last reset (reset != 0 clears them).  Stages a call did not run add 0.
+ * In the binned form with keys derived in the call, the derivation runs in
+ * the same launch as the scatter and its time is counted in bin_ms.
  */
 typedef struct {
     double derive_ms;

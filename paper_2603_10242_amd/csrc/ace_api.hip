@@ -278,6 +278,9 @@ DevBlock dev_block(const ace_block &k)
     return d;
 }
 
+// Workgroups of the count pass: each adds to a block's count at most once.
+constexpr uint64_t kCountWGs = 256;
+
 // Verify-kernel launches for the plan's key source, persistence and record form.
 template <bool PT, bool AT>
 void launch_ordered_t(unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
@@ -337,13 +340,17 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     ks.n_id = keys->n_id;
     ks.mid = nullptr;
     ks.rev = nullptr;
+    // keys derived in the call: in the binned form the derivation shares the
+    // scatter's launch (the two are independent), else it runs first
+    bool derive_with_scatter = false;
     if (!p.rev) {
         ks.mid = keys->d_mid;
     } else if (p.per_tx) {
         ks.rev = keys->d_rev;
     } else {
         uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
-        if (keys->n_id) {
+        derive_with_scatter = binned && keys->n_id && (graph || p.total_tx);
+        if (keys->n_id && !derive_with_scatter) {
             const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
             hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, s, keys->d_rev, keys->n_id,
                                (uint8_t *)nullptr, mid, hp);
@@ -368,6 +375,12 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
             if ((rc = launch_status("k_verify_ordered launch"))) return rc;
         }
         prof_mark(prof, 3, s);
+        if (graph || p.total_tx) {
+            hipLaunchKernelGGL(k_count, dim3(grid_for(graph ? (p.total_tx + kTile - 1) / kTile + p.n_blocks
+                                                            : p.total_tiles, 1, kCountWGs)),
+                               dim3(kWG), 0, s, bt);
+            if ((rc = launch_status("k_count launch"))) return rc;
+        }
         prof_mark(prof, 4, s);
         return ACE_OK;
     }
@@ -387,9 +400,16 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     if ((rc = launch_status("k_bin_count launch"))) return rc;
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
     if ((rc = launch_status("k_bin_scan launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm, rec,
-                       pos_of);
-    if ((rc = launch_status("k_bin_scatter launch"))) return rc;
+    if (derive_with_scatter) {
+        const unsigned gd = (unsigned)((keys->n_id + kWG - 1) / kWG);
+        hipLaunchKernelGGL(k_scatter_derive, dim3(gtiles + gd), dim3(kWG), 0, s, bt, ctrl, keys->n_id,
+                           perm, rec, pos_of, gtiles, keys->d_rev, const_cast<uint32_t *>(ks.mid), hp);
+        if ((rc = launch_status("k_scatter_derive launch"))) return rc;
+    } else {
+        hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm,
+                           rec, pos_of);
+        if ((rc = launch_status("k_bin_scatter launch"))) return rc;
+    }
     prof_mark(prof, 2, s);
 
     {
@@ -401,6 +421,8 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     prof_mark(prof, 3, s);
     hipLaunchKernelGGL(k_finalize, dim3(gtiles), dim3(kWG), 0, s, bt, pos_of, vperm);
     if ((rc = launch_status("k_finalize launch"))) return rc;
+    hipLaunchKernelGGL(k_count, dim3(grid_for(tiles_bound, 1, kCountWGs)), dim3(kWG), 0, s, bt);
+    if ((rc = launch_status("k_count launch"))) return rc;
     prof_mark(prof, 4, s);
     return ACE_OK;
 }

@@ -53,9 +53,14 @@ struct Batch {
 };
 
 // Control words of a bucketed pass (start of the workspace).
+// Copies of the per-bin counters: workgroup w of the count and scatter passes
+// uses copy w % kCopies, so a counter sees a few hundred atomics instead of
+// one per workgroup (same-address atomics serialize).
+constexpr uint32_t kCopies = 32;
+
 struct Ctrl {
-    uint32_t hist[kBins];    // transactions per bin
-    uint32_t cursor[kBins];  // next free position per bin (scatter)
+    uint32_t hist[kBins * kCopies];    // transactions per (bin, copy)
+    uint32_t cursor[kBins * kCopies];  // next free position per (bin, copy) (scatter)
     uint32_t ostart[kBins];  // bins in order o = 63 - bin (longest first): padded start
     uint32_t ocount[kBins];  // real transactions
     uint32_t opad[kBins];    // count rounded up to a multiple of 64

@@ -29,13 +29,19 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-// 16-byte load from a 4-byte aligned address.
+// Loads from 4-byte aligned addresses in device memory, issued as global
+// (not flat) loads: they then count only against the vector memory counter,
+// so waiting for the round constants' scalar loads does not also wait for
+// them.
+typedef const __attribute__((address_space(1))) uint32_t *gptr;
 __device__ __forceinline__ U4 load16(const uint32_t *p)
 {
+    const gptr g = (gptr)p;
     U4 v;
-    __builtin_memcpy(&v, p, 16);
+    v.x = g[0]; v.y = g[1]; v.z = g[2]; v.w = g[3];
     return v;
 }
+__device__ __forceinline__ uint32_t load32(const uint32_t *p) { return *(gptr)p; }
 
 // Block count and totals of a call: kernel arguments, or the device header
 // of a graph replay.
@@ -45,14 +51,23 @@ struct Totals {
     uint64_t tx, tiles, waves;
 };
 
+// The same value in every lane, made visible to the compiler as such, so
+// that loops bounded by it stay scalar.
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)uniform32((uint32_t)(v >> 32)) << 32) | uniform32((uint32_t)v);
+}
+
 __device__ __forceinline__ Totals totals(const Batch &bt)
 {
     Totals t;
     if (bt.hdr) {
-        t.n_blocks = bt.hdr->n_blocks;
-        t.tx = bt.hdr->total_tx;
-        t.tiles = bt.hdr->total_tiles;
-        t.waves = bt.hdr->total_waves;
+        // one header read by every lane at the same address
+        t.n_blocks = uniform32(bt.hdr->n_blocks);
+        t.tx = uniform64(bt.hdr->total_tx);
+        t.tiles = uniform64(bt.hdr->total_tiles);
+        t.waves = uniform64(bt.hdr->total_waves);
         t.inline_one = false;
     } else {
         t.n_blocks = bt.n_blocks;
@@ -360,7 +375,6 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
 
     const uint64_t L = t.L;
     const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;  // message blocks
-    const uint32_t last_step = ATTEST ? nb + 1 : nb;                // + HMAC inner (paper form) + outer
     const uintptr_t addr = reinterpret_cast<uintptr_t>(t.msg);
     const uint32_t sh = (uint32_t)addr & 3u;
     const uint32_t sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
@@ -377,89 +391,100 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
     const uint64_t bits = ((ATTEST ? 0 : 64) + L) << 3;
     const uint32_t len_hi = (uint32_t)(bits >> 32);
     const uint32_t len_lo = (uint32_t)bits;
-    uint32_t bind = 0;  // paper form: OR of SHA-256(P) ^ obj_hash
 
-    for (uint32_t b = 0;; ++b) {
-        const bool run = live && b <= last_step;
+    // Message blocks.  Only these vary in number between lanes (in the binned
+    // kernel not at all within a wave); the fixed-form blocks after the loop
+    // run once for every lane.
+    const uint32_t *q = A0;  // dword 16 b of the message area, advanced per block
+    int64_t rb = (int64_t)L;  // message bytes from this block on
+    for (uint32_t b = 0;; ++b, q += 16, rb -= 64) {
+        const bool run = live && b < nb;
         if (__ballot(run) == 0) break;
         if (run) {
             uint32_t W[16];
-            State in;
-            if (b < nb) {
-                in = S;
-                const uint64_t g0 = 16ull * b;
-                const int64_t rb = (int64_t)L - 64 * (int64_t)b;  // message bytes from this block on
-                uint32_t D[17];
-                if (t.overread_ok || rb >= 64) {
-                    // whole 16-byte loads; past the message end they only read bytes of
-                    // the same block's message area, which the padding overwrites
-                    const uint32_t *q = A0 + g0;
-                    const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
-                    D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
-                    D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
-                    D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
-                    D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
-                    const uint64_t k16 = g0 + 16;
-                    D[16] = t.overread_ok ? q[16] : A0[k16 < last ? k16 : last];
-                } else {
-                    // the last message before the end of its block's area: every
-                    // dword address is clamped to one that holds message bytes
-#pragma unroll
-                    for (int k = 0; k < 17; ++k) {
-                        const uint64_t idx = g0 + k;
-                        D[k] = A0[idx < last ? idx : last];
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
-                if (rb < 64) {
-                    // padding: word jf holds byte rb (the 0x80 marker) after its c
-                    // message bytes; earlier words are message, later ones zero
-                    const int32_t r0 = (int32_t)rb;
-                    const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
-                    const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
-                    const uint32_t keep = ~(0xFFFFFFFFu >> c8);
-                    const uint32_t pad = 0x80000000u >> c8;
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) {
-                        const uint32_t part = (W[j] & keep) | pad;
-                        W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
-                    }
-                    if (b + 1 == nb) {
-                        W[14] = len_hi;
-                        W[15] = len_lo;
-                    }
-                }
-            } else if (ATTEST && b == nb) {
-                // S = SHA-256(P): compare with obj_hash, then the HMAC inner block
-                // over obj_hash || domain (40 bytes, bit length (64 + 40) * 8)
-                const uint32_t *ap = reinterpret_cast<const uint32_t *>(t.tag);
-                const U4 a0 = load16(ap), a1 = load16(ap + 4);
-                const uint32_t d0 = ap[8], d1 = ap[9];
-                W[0] = bswap32(a0.x); W[1] = bswap32(a0.y); W[2] = bswap32(a0.z); W[3] = bswap32(a0.w);
-                W[4] = bswap32(a1.x); W[5] = bswap32(a1.y); W[6] = bswap32(a1.z); W[7] = bswap32(a1.w);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) bind = or_xor(bind, S.h[i], W[i]);
-                W[8] = bswap32(d0);
-                W[9] = bswap32(d1);
-                W[10] = 0x80000000u;
-#pragma unroll
-                for (int i = 11; i < 15; ++i) W[i] = 0u;
-                W[15] = (64u + 40u) * 8u;
-                in = ipad;
+            uint32_t D[17];
+            if (t.overread_ok || rb >= 64) {
+                // whole 16-byte loads; past the message end they only read bytes of
+                // the same block's message area, which the padding overwrites
+                const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
+                D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
+                D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
+                D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
+                D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
+                const uint64_t k16 = 16ull * b + 16;
+                D[16] = load32(t.overread_ok ? q + 16 : A0 + (k16 < last ? k16 : last));
             } else {
-                // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
-                in = opad;
+                // the last message before the end of its block's area: every
+                // dword address is clamped to one that holds message bytes
 #pragma unroll
-                for (int i = 0; i < 8; ++i) W[i] = S.h[i];
-                W[8] = 0x80000000u;
-#pragma unroll
-                for (int i = 9; i < 15; ++i) W[i] = 0u;
-                W[15] = 768u;
+                for (int k = 0; k < 17; ++k) {
+                    const uint64_t idx = 16ull * b + k;
+                    D[k] = load32(A0 + (idx < last ? idx : last));
+                }
             }
-            compress_block(in, W);
-            S = in;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+            if (rb < 64) {
+                // padding: word jf holds byte rb (the 0x80 marker) after its c
+                // message bytes; earlier words are message, later ones zero
+                const int32_t r0 = (int32_t)rb;
+                const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
+                const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
+                const uint32_t keep = ~(0xFFFFFFFFu >> c8);
+                const uint32_t pad = 0x80000000u >> c8;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t part = (W[j] & keep) | pad;
+                    W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
+                }
+                if (b + 1 == nb) {
+                    W[14] = len_hi;
+                    W[15] = len_lo;
+                }
+            }
+            compress_block(S, W);
         }
+    }
+
+    uint32_t bind = 0;  // paper form: OR of SHA-256(P) ^ obj_hash
+    if constexpr (ATTEST) {
+        // S = SHA-256(P): compare with obj_hash, then the HMAC inner block over
+        // obj_hash || domain (40 bytes, bit length (64 + 40) * 8)
+        uint32_t W[16];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) W[i] = 0;
+        if (live) {
+            const uint32_t *ap = reinterpret_cast<const uint32_t *>(t.tag);
+            const U4 a0 = load16(ap), a1 = load16(ap + 4);
+            const uint32_t d0 = ap[8], d1 = ap[9];
+            W[0] = bswap32(a0.x); W[1] = bswap32(a0.y); W[2] = bswap32(a0.z); W[3] = bswap32(a0.w);
+            W[4] = bswap32(a1.x); W[5] = bswap32(a1.y); W[6] = bswap32(a1.z); W[7] = bswap32(a1.w);
+            W[8] = bswap32(d0);
+            W[9] = bswap32(d1);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bind = or_xor(bind, S.h[i], W[i]);
+        W[10] = 0x80000000u;
+#pragma unroll
+        for (int i = 11; i < 15; ++i) W[i] = 0u;
+        W[15] = (64u + 40u) * 8u;
+        State T = ipad;
+        compress_block(T, W);
+        S = T;
+    }
+
+    // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
+    {
+        uint32_t W[16];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) W[i] = S.h[i];
+        W[8] = 0x80000000u;
+#pragma unroll
+        for (int i = 9; i < 15; ++i) W[i] = 0u;
+        W[15] = 768u;
+        State T = opad;
+        compress_block(T, W);
+        S = T;
     }
 
     bool ok = false;
@@ -498,7 +523,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
 // one block; the ballot is that block's two bitmask words.
 // ------------------------------------------------------------------------------------------
 template <bool PER_TX_KEYS, bool ATTEST>
-__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 6) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
+__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? 6 : 7)) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
 {
     __shared__ HkdfPrep prep;
     if constexpr (PER_TX_KEYS) {
@@ -523,8 +548,6 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 6) k_verify_o
         if (lane_id() == 0) {
             d.bitmask[i0 >> 5] = (uint32_t)m;
             if (i0 + 32 < d.n) d.bitmask[(i0 >> 5) + 1] = (uint32_t)(m >> 32);
-            const unsigned c = __popcll(m);
-            if (c) atomicAdd(d.count, (unsigned long long)c);
         }
     }
 }
@@ -537,9 +560,11 @@ __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
     const Totals T = totals(bt);
     const uint32_t t = blockIdx.x * kWG + threadIdx.x;
     for (uint32_t b = t; b < T.n_blocks; b += gridDim.x * kWG) *get_block(bt, T, b).count = 0;
-    if (ctrl && blockIdx.x == 0 && threadIdx.x < kBins) {
-        ctrl->hist[threadIdx.x] = 0;
-        ctrl->cursor[threadIdx.x] = 0;
+    if (ctrl && blockIdx.x == 0) {
+        for (uint32_t k = threadIdx.x; k < kBins * kCopies; k += kWG) {
+            ctrl->hist[k] = 0;
+            ctrl->cursor[k] = 0;
+        }
         if (threadIdx.x == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
     }
 }
@@ -553,6 +578,7 @@ __device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i, uin
 
 __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl, uint32_t n_id)
 {
+    constexpr int kPer = kTile / kWG;
     __shared__ uint32_t h[kBins];
     if (threadIdx.x < kBins) h[threadIdx.x] = 0;
     __syncthreads();
@@ -560,21 +586,29 @@ __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl, uint32_
     for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
         const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
-        for (uint32_t k = threadIdx.x; k < kTile; k += kWG) {
-            const uint64_t i = i0 + k;
-            if (i < d.n) atomicAdd(&h[bin_of_length(tx_length(d, i, n_id))], 1u);
+        uint32_t bins[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {  // all loads first, then the counting
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+            bins[k] = i < d.n ? bin_of_length(tx_length(d, i, n_id)) : kBins;
         }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (bins[k] < kBins) atomicAdd(&h[bins[k]], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kBins && h[threadIdx.x]) atomicAdd(&ctrl->hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kBins && h[threadIdx.x])
+        atomicAdd(&ctrl->hist[threadIdx.x * kCopies + blockIdx.x % kCopies], h[threadIdx.x]);
 }
 
-// One wave: bins laid out longest first so the longest waves start first.
+// One wave: bins laid out longest first so the longest waves start first;
+// within a bin, copy c of its counters starts after copies 0 .. c-1.
 __global__ void k_bin_scan(Ctrl *ctrl)
 {
     const uint32_t o = threadIdx.x;          // order position
     const uint32_t bin = kBins - 1 - o;
-    const uint32_t cnt = ctrl->hist[bin];
+    uint32_t cnt = 0;
+    for (uint32_t c = 0; c < kCopies; ++c) cnt += ctrl->hist[bin * kCopies + c];
     const uint32_t pad = (cnt + 63u) & ~63u;
     __shared__ uint32_t s[kBins];
     s[o] = pad;
@@ -584,20 +618,25 @@ __global__ void k_bin_scan(Ctrl *ctrl)
     ctrl->ostart[o] = start;
     ctrl->ocount[o] = cnt;
     ctrl->opad[o] = pad;
-    ctrl->cursor[bin] = start;
+    uint32_t at = start;
+    for (uint32_t c = 0; c < kCopies; ++c) {
+        ctrl->cursor[bin * kCopies + c] = at;
+        at += ctrl->hist[bin * kCopies + c];
+    }
     if (o == kBins - 1) ctrl->total_pos = start + pad;
 }
 
-__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint32_t n_id,
-                                                     unsigned long long *__restrict__ perm,
-                                                     TxRec *__restrict__ rec,
-                                                     uint32_t *__restrict__ pos_of)
+// Scatter of the tiles wg, wg + n_wg, ... into bin order (one workgroup).
+__device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_t n_id,
+                                            unsigned long long *__restrict__ perm,
+                                            TxRec *__restrict__ rec, uint32_t *__restrict__ pos_of,
+                                            uint32_t wg, uint32_t n_wg)
 {
     constexpr int kPer = kTile / kWG;
     __shared__ uint32_t cnt[kBins];
     __shared__ uint32_t base[kBins];
     const Totals T = totals(bt);
-    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+    for (uint64_t tile = wg; tile < T.tiles; tile += n_wg) {
         const uint32_t b = find_block<0>(bt, T, tile);
         const DevBlock d = get_block(bt, T, b);
         const uint64_t i0 = (tile - d.tile0) * kTile;
@@ -625,7 +664,8 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
         }
         __syncthreads();
         if (threadIdx.x < kBins && cnt[threadIdx.x])
-            base[threadIdx.x] = atomicAdd(&ctrl->cursor[threadIdx.x], cnt[threadIdx.x]);
+            base[threadIdx.x] = atomicAdd(&ctrl->cursor[threadIdx.x * kCopies + wg % kCopies],
+                                          cnt[threadIdx.x]);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -641,12 +681,47 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
     }
 }
 
+__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint32_t n_id,
+                                                     unsigned long long *__restrict__ perm,
+                                                     TxRec *__restrict__ rec,
+                                                     uint32_t *__restrict__ pos_of)
+{
+    bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, blockIdx.x, gridDim.x);
+}
+
+// The scatter and the key derivation of a keyset of kind REV are independent,
+// so they share one launch: workgroups below n_scatter scatter (memory-bound),
+// the rest derive one identity per lane (VALU-bound); the derivation starts
+// on CUs as the scatter's workgroups drain instead of after all of them.
+__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_scatter_derive(Batch bt, Ctrl *ctrl, uint32_t n_id,
+                                                       unsigned long long *__restrict__ perm,
+                                                       TxRec *__restrict__ rec,
+                                                       uint32_t *__restrict__ pos_of,
+                                                       uint32_t n_scatter,
+                                                       const uint8_t *__restrict__ rev,
+                                                       uint32_t *__restrict__ mid_out,
+                                                       HkdfParams hp)
+{
+    if (blockIdx.x < n_scatter) {
+        bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, blockIdx.x, n_scatter);
+        return;
+    }
+    __shared__ HkdfPrep prep;
+    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
+    __syncthreads();
+    const uint32_t j = (blockIdx.x - n_scatter) * kWG + threadIdx.x;
+    derive_identity(rev, n_id, j, j, prep, nullptr, mid_out);
+}
+
+// Wave tiles a persistent verify wave takes per atomic grab.
+constexpr uint32_t kGrab = 8;
+
 // ------------------------------------------------------------------------------------------
 // k_verify, binned form: wave tile w covers bin-order positions 64w..64w+63,
 // all in one bin; verdicts go to a bin-order bitmap.
 // ------------------------------------------------------------------------------------------
 template <bool PER_TX_KEYS, bool PERSISTENT, bool ATTEST>
-__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST && PERSISTENT ? 6 : 7)) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
+__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PERSISTENT ? 6 : 7) : 8)) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
                                                        const TxRec *__restrict__ rec,
@@ -669,14 +744,23 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST && PE
     const uint32_t lane = lane_id();
     uint32_t w = PERSISTENT ? 0u
                             : blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t left = 0;  // persistent: wave tiles left of the last grab
     for (;;) {
         if constexpr (PERSISTENT) {
-            // Every lane takes part in the atomic (lane 0 adds 1, the others 0)
-            // so no divergent branch precedes the readfirstlane: with the
-            // atomic under `if (lane == 0)` the compiler may split this loop
-            // per lane and leave lanes 1..63 re-reading a stale tile forever.
-            const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? 1u : 0u);
-            w = __builtin_amdgcn_readfirstlane(v);
+            if (left == 0) {
+                // Every lane takes part in the atomic (lane 0 adds kGrab, the
+                // others 0) so no divergent branch precedes the readfirstlane:
+                // with the atomic under `if (lane == 0)` the compiler may split
+                // this loop per lane and leave lanes 1..63 re-reading a stale
+                // tile forever.  A grab of kGrab tiles keeps the counter's
+                // same-address atomics few.
+                const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? kGrab : 0u);
+                w = __builtin_amdgcn_readfirstlane(v);
+                left = kGrab;
+            } else {
+                ++w;
+            }
+            --left;
         }
         if (w >= nwaves) break;
         const uint32_t k0 = w << 6;
@@ -720,13 +804,11 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST && PE
 __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__restrict__ pos_of,
                                                   const uint32_t *__restrict__ vperm)
 {
-    __shared__ unsigned long long part[kWavesPerWG];
     const uint32_t lane = lane_id();
     const Totals T = totals(bt);
     for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
         const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
-        unsigned long long acc = 0;
 #pragma unroll
         for (int it = 0; it < kTile / kWG; ++it) {  // uniform trip count: the ballot sees every lane
             const uint64_t i = i0 + threadIdx.x + (uint64_t)it * kWG;
@@ -741,9 +823,36 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
                 d.bitmask[base >> 5] = (uint32_t)m;
                 if (base + 32 < d.n) d.bitmask[(base >> 5) + 1] = (uint32_t)(m >> 32);
             }
-            acc += __popcll(m);
         }
-        if (lane == 0) part[threadIdx.x >> 6] = acc;
+    }
+}
+
+// Valid counts from the finished bitmasks (their unused tail bits are 0):
+// workgroup w sums a contiguous run of tiles, one 64-word tile per wave at a
+// time, and adds each block's part with one atomic, so a counter sees at most
+// gridDim.x atomics.
+__global__ void __launch_bounds__(kWG) k_count(Batch bt)
+{
+    __shared__ unsigned long long part[kWavesPerWG];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    const Totals T = totals(bt);
+    const uint64_t per = (T.tiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * per;
+    const uint64_t t1 = t0 + per < T.tiles ? t0 + per : T.tiles;
+    for (uint64_t t = t0; t < t1;) {
+        const DevBlock d = get_block(bt, T, find_block<0>(bt, T, t));
+        const uint64_t dt_end = uniform64(d.tile0 + (d.n + kTile - 1) / kTile);
+        const uint64_t end = dt_end < t1 ? dt_end : t1;
+        const uint64_t words = (d.n + 31) / 32;
+        unsigned long long acc = 0;
+        for (uint64_t u = t + wave; u < end; u += kWavesPerWG) {
+            const uint64_t w = (u - d.tile0) * (kTile / 32) + lane;  // kTile / 32 == 64 words
+            if (w < words) acc += __popc(d.bitmask[w]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+        if (lane == 0) part[wave] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long s = 0;
@@ -751,6 +860,7 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
             if (s) atomicAdd(d.count, s);
         }
         __syncthreads();
+        t = end;
     }
 }
 
@@ -770,9 +880,11 @@ __global__ void __launch_bounds__(kPlanWG) k_plan(const DevBlock *__restrict__ s
     uint32_t n = *src_n;
     if (n > max_blocks) n = max_blocks;
     if (t < 3) carry[t] = 0;
-    if (ctrl && t < kBins) {
-        ctrl->hist[t] = 0;
-        ctrl->cursor[t] = 0;
+    if (ctrl) {
+        for (uint32_t k = t; k < kBins * kCopies; k += kPlanWG) {
+            ctrl->hist[k] = 0;
+            ctrl->cursor[k] = 0;
+        }
         if (t == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
     }
     __syncthreads();

@@ -190,7 +190,8 @@ def test_workspace_size_layout(lib):
     one = (ace.ace_block * 1)(_block(ace, n=1_000_000))
     ordered = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_ORDERED)
     binned = lib.ace_verify_workspace_size(ctypes.byref(ks), one, 1, ace.ACE_BUCKETED)
-    assert 0 < ordered < 4096
+    # ordered: the control words only (per-bin counters in 32 copies)
+    assert 0 < ordered < 20 * 1024
     # binned: 8 B permutation + 16 B record + 4 B position + 1 bit per transaction,
     # plus 64 bins of padding
     assert binned >= ordered + 28 * 1_000_000
