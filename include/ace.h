@@ -324,8 +324,9 @@ ACE_API int ace_stream_create_host(ace_host_verify_fn fn, void *user, size_t are
  * kernel and the finalize pass.  ace_profile_read() waits for the recorded
  * events and returns the summed milliseconds of all profiled calls since the
  * last reset (reset != 0 clears them).  Stages a call did not run add 0.
- * In the binned form with keys derived in the call, the derivation runs in
- * the same launch as the scatter and its time is counted in bin_ms.
+ * In the binned form with keys derived in the call, the derivation runs on
+ * a second stream beside the binning passes; the derive stage then reads
+ * about 0 and bin_ms covers both, up to the join before the verify kernel.
  */
 typedef struct {
     double derive_ms;

@@ -278,6 +278,32 @@ DevBlock dev_block(const ace_block &k)
     return d;
 }
 
+// A second stream per thread and device on which the key derivation runs
+// beside the binning passes: forked from and joined back to the caller's
+// stream with events (under graph capture, two branches of the graph).  The
+// streams and events live until the process ends.
+struct Fork {
+    int dev;
+    hipStream_t aux;
+    hipEvent_t fork, join;
+};
+
+Fork *fork_ctx()
+{
+    thread_local std::vector<Fork> forks;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto &f : forks)
+        if (f.dev == dev) return &f;
+    Fork f{dev, nullptr, nullptr, nullptr};
+    if (hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    forks.push_back(f);
+    return &forks.back();
+}
+
 // Workgroups of the count pass: each adds to a block's count at most once.
 constexpr uint64_t kCountWGs = 256;
 
@@ -340,21 +366,29 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     ks.n_id = keys->n_id;
     ks.mid = nullptr;
     ks.rev = nullptr;
-    // keys derived in the call: in the binned form the derivation shares the
-    // scatter's launch (the two are independent), else it runs first
-    bool derive_with_scatter = false;
+    // keys derived in the call: in the binned form the derivation (VALU-bound)
+    // runs on a second stream beside the binning passes (memory-bound), which
+    // do not depend on it; the verify kernel waits for both
+    Fork *fk = nullptr;
     if (!p.rev) {
         ks.mid = keys->d_mid;
     } else if (p.per_tx) {
         ks.rev = keys->d_rev;
     } else {
         uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
-        derive_with_scatter = binned && keys->n_id && (graph || p.total_tx);
-        if (keys->n_id && !derive_with_scatter) {
+        if (keys->n_id) {
             const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
-            hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, s, keys->d_rev, keys->n_id,
+            hipStream_t ds = s;
+            if (binned && (graph || p.total_tx) && (fk = fork_ctx())) {
+                if ((rc = check_hip(hipEventRecord(fk->fork, s), "hipEventRecord"))) return rc;
+                if ((rc = check_hip(hipStreamWaitEvent(fk->aux, fk->fork, 0), "hipStreamWaitEvent")))
+                    return rc;
+                ds = fk->aux;
+            }
+            hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, ds, keys->d_rev, keys->n_id,
                                (uint8_t *)nullptr, mid, hp);
             if ((rc = launch_status("k_derive launch"))) return rc;
+            if (fk && (rc = check_hip(hipEventRecord(fk->join, fk->aux), "hipEventRecord"))) return rc;
         }
         ks.mid = mid;
     }
@@ -400,16 +434,10 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     if ((rc = launch_status("k_bin_count launch"))) return rc;
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
     if ((rc = launch_status("k_bin_scan launch"))) return rc;
-    if (derive_with_scatter) {
-        const unsigned gd = (unsigned)((keys->n_id + kWG - 1) / kWG);
-        hipLaunchKernelGGL(k_scatter_derive, dim3(gtiles + gd), dim3(kWG), 0, s, bt, ctrl, keys->n_id,
-                           perm, rec, pos_of, gtiles, keys->d_rev, const_cast<uint32_t *>(ks.mid), hp);
-        if ((rc = launch_status("k_scatter_derive launch"))) return rc;
-    } else {
-        hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm,
-                           rec, pos_of);
-        if ((rc = launch_status("k_bin_scatter launch"))) return rc;
-    }
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm, rec,
+                       pos_of);
+    if ((rc = launch_status("k_bin_scatter launch"))) return rc;
+    if (fk && (rc = check_hip(hipStreamWaitEvent(s, fk->join, 0), "hipStreamWaitEvent"))) return rc;
     prof_mark(prof, 2, s);
 
     {

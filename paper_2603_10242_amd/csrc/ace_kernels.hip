@@ -689,31 +689,7 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint3
     bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, blockIdx.x, gridDim.x);
 }
 
-// The scatter and the key derivation of a keyset of kind REV are independent,
-// so they share one launch: workgroups below n_scatter scatter (memory-bound),
-// the rest derive one identity per lane (VALU-bound); the derivation starts
-// on CUs as the scatter's workgroups drain instead of after all of them.
-__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_scatter_derive(Batch bt, Ctrl *ctrl, uint32_t n_id,
-                                                       unsigned long long *__restrict__ perm,
-                                                       TxRec *__restrict__ rec,
-                                                       uint32_t *__restrict__ pos_of,
-                                                       uint32_t n_scatter,
-                                                       const uint8_t *__restrict__ rev,
-                                                       uint32_t *__restrict__ mid_out,
-                                                       HkdfParams hp)
-{
-    if (blockIdx.x < n_scatter) {
-        bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, blockIdx.x, n_scatter);
-        return;
-    }
-    __shared__ HkdfPrep prep;
-    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
-    __syncthreads();
-    const uint32_t j = (blockIdx.x - n_scatter) * kWG + threadIdx.x;
-    derive_identity(rev, n_id, j, j, prep, nullptr, mid_out);
-}
-
-// Wave tiles a persistent verify wave takes per atomic grab.
+// Most wave tiles a persistent verify wave takes per atomic grab.
 constexpr uint32_t kGrab = 8;
 
 // ------------------------------------------------------------------------------------------
@@ -739,8 +715,12 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
     }
     __syncthreads();
     const Totals T = totals(bt);
-    const uint32_t total = ctrl->total_pos;
+    const uint32_t total = uniform32(ctrl->total_pos);
     const uint32_t nwaves = total >> 6;
+    // persistent: tiles per grab, up to kGrab while every wave still gets
+    // about four grabs (small batches take one tile at a time)
+    uint32_t grab = nwaves / (gridDim.x * kWavesPerWG * 4u);
+    grab = grab < 1u ? 1u : (grab > kGrab ? kGrab : grab);
     const uint32_t lane = lane_id();
     uint32_t w = PERSISTENT ? 0u
                             : blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -748,15 +728,15 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
     for (;;) {
         if constexpr (PERSISTENT) {
             if (left == 0) {
-                // Every lane takes part in the atomic (lane 0 adds kGrab, the
+                // Every lane takes part in the atomic (lane 0 adds the grab, the
                 // others 0) so no divergent branch precedes the readfirstlane:
                 // with the atomic under `if (lane == 0)` the compiler may split
                 // this loop per lane and leave lanes 1..63 re-reading a stale
-                // tile forever.  A grab of kGrab tiles keeps the counter's
+                // tile forever.  Grabs of several tiles keep the counter's
                 // same-address atomics few.
-                const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? kGrab : 0u);
+                const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? grab : 0u);
                 w = __builtin_amdgcn_readfirstlane(v);
-                left = kGrab;
+                left = grab;
             } else {
                 ++w;
             }
