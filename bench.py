@@ -14,7 +14,6 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
-import gc
 import json
 import os
 import sys
@@ -104,6 +103,14 @@ def cpu_baseline(w, seconds: float) -> dict:
     if sample % 32 == 0 and not np.array_equal(mask, truth):
         raise SystemExit("oracle disagrees with the generator's truth mask")
     step_s = t_derive + t_verify * (w.n / sample)
+    # context: the same HMAC check with OpenSSL's EVP_MAC (an optimized CPU library), all cores
+    from paper_2603_10242_amd import workload as W
+    t = time.perf_counter()
+    ossl = W.client_sign(keys, w.msg, w.off[: sample + 1], w.ids[:sample], threads)
+    t_ossl = time.perf_counter() - t
+    if sample % 32 == 0 and not np.array_equal(
+            W.pack_bits(np.all(ossl == w.tags[:sample], axis=1)), mask):
+        raise SystemExit("OpenSSL and the oracle disagree")
     # one thread, for the per-transaction cost the paper quotes for one core
     one = min(w.n, 50_000)
     t = time.perf_counter()
@@ -114,6 +121,7 @@ def cpu_baseline(w, seconds: float) -> dict:
                       "(%.2f s), verify time scaled to the whole batch" %
                       (w.n_id, t_derive, sample, w.n, t_verify),
             "single_thread_us_per_tx": us_per_tx_1t,
+            "openssl_hmac_per_s": sample / t_ossl,
             "host_cpu": host_cpu_model()}
 
 
@@ -218,43 +226,30 @@ def bench_batching(args) -> dict:
 
 def drive(stream, pool, starts, sizes, arrivals, threads: int = 8):
     """Open-loop load: request k arrives at arrivals[k] (monotonic seconds) and is
-    submitted then by one of `threads` submitter threads.  Returns the arrival,
-    admit and completion times of every request."""
-    import threading
+    submitted then by one of `threads` native submitter threads (the load
+    generator is C, so the interpreter's pauses stay out of the latencies).
+    Returns the arrival, submit, admit and completion times of every request."""
+    import ctypes
+    from paper_2603_10242_amd import ace
+    from paper_2603_10242_amd import workload as W
+    fn = ctypes.cast(ace.load().ace_verify_stream, ctypes.c_void_p).value
+    tickets, submit, masks, mask_words, counts = W.client_drive(
+        fn, stream._h.value, pool, starts, sizes, arrivals, threads)
     n = len(sizes)
-    tickets = [None] * n
-
-    def submitter(j):
-        for k in range(j, n, threads):
-            delay = arrivals[k] - time.monotonic()
-            if delay > 0:
-                time.sleep(delay)
-            lo, hi = int(starts[k]), int(starts[k] + sizes[k])
-            tickets[k] = stream.submit(pool.msg, pool.off[lo:hi + 1], pool.ids[lo:hi],
-                                       pool.tags[lo:hi])
-
-    ths = [threading.Thread(target=submitter, args=(j,)) for j in range(threads)]
-    # the load generator's own pauses (garbage collection) are kept out of the run
-    gc.collect()
-    gc.disable()
-    try:
-        for t in ths:
-            t.start()
-        for t in ths:
-            t.join()
-    finally:
-        gc.enable()
     done = np.zeros(n)
     admit = np.zeros(n)
-    submit = np.zeros(n)
     bad = 0
-    for k, t in enumerate(tickets):
-        mask, count = stream.result(t)
+    for k in range(n):
+        t = ace.Ticket(int(tickets[k]), int(sizes[k]), None, None)
+        stream.poll(t, True)
         lo, hi = int(starts[k]), int(starts[k] + sizes[k])
-        if count != int(pool.truth[lo:hi].sum()):
+        if int(counts[k]) != int(pool.truth[lo:hi].sum()):
             bad += 1
-        submit[k], admit[k], done[k] = stream.times(t)
+        _, admit[k], done[k] = stream.times(t)
         stream.release(t)
+    words = masks[int(mask_words[0]):int(mask_words[0]) + (int(sizes[0]) + 31) // 32] if n else None
+    if n and not np.array_equal(words, W.pack_bits(pool.truth[int(starts[0]):int(starts[0] + sizes[0])])):
+        bad += 1
     if bad:
         raise SystemExit("RESULT MISMATCH in %d serving requests" % bad)
     return np.asarray(arrivals), submit, admit, done

@@ -30,6 +30,7 @@ KIND_TAG, KIND_MSG, KIND_KEY = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _CLIENT_SRC = os.path.join(_HERE, "attest_client.c")
+_DRIVER_SRC = os.path.join(_HERE, "serving_client.c")
 _CLIENT_LIB = os.path.join(_HERE, "libace_client.so")
 _client = None
 
@@ -38,7 +39,7 @@ def build_client(force: bool = True) -> str:
     if force or not os.path.exists(_CLIENT_LIB):
         tmp = _CLIENT_LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp,
-                               _CLIENT_SRC, "-lcrypto", "-lpthread"])
+                               _CLIENT_SRC, _DRIVER_SRC, "-lcrypto", "-lpthread"])
         os.replace(tmp, _CLIENT_LIB)
     return _CLIENT_LIB
 
@@ -54,6 +55,8 @@ def _lib():
         lib.client_sign.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
         lib.client_digest.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
         lib.client_hash_chain.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_int]
+        lib.client_drive.argtypes = [vp] * 10 + [ctypes.c_uint64, ctypes.c_int] + [vp] * 4
+        lib.client_drive.restype = ctypes.c_int
         _client = lib
     return _client
 
@@ -441,6 +444,37 @@ def client_merkle_root(data: np.ndarray, off: np.ndarray) -> bytes:
             nxt.append(level[-1])
         level = nxt
     return level[0]
+
+
+def client_drive(verify_stream_addr: int, stream_handle: int, pool, starts, sizes, arrivals,
+                 threads: int = 8):
+    """Open-loop submission of requests (starts[k], sizes[k]) of the pool at
+    arrivals[k] (monotonic seconds) by native threads through the library's
+    ace_verify_stream (its address).  Returns (tickets, submit times, masks,
+    mask word offsets, counts); the caller polls and reads the tickets."""
+    starts = np.ascontiguousarray(starts, np.uint64)
+    sizes = np.ascontiguousarray(sizes, np.uint64)
+    arrivals = np.ascontiguousarray(arrivals, np.float64)
+    n = sizes.shape[0]
+    words = (sizes + 31) // 32
+    mask_words = np.zeros(n, np.uint64)
+    np.cumsum(words[:-1], out=mask_words[1:])
+    masks = np.zeros(max(1, int(words.sum())), np.uint32)
+    counts = np.zeros(n, np.uint64)
+    tickets = np.zeros(n, np.uint64)
+    submit = np.zeros(n, np.float64)
+    msg = np.ascontiguousarray(pool.msg, np.uint8)
+    off = np.ascontiguousarray(pool.off, np.uint64)
+    ids = np.ascontiguousarray(pool.ids, np.uint32)
+    tags = np.ascontiguousarray(pool.tags, np.uint8)
+    rc = _lib().client_drive(verify_stream_addr, stream_handle, msg.ctypes.data, off.ctypes.data,
+                             ids.ctypes.data, tags.ctypes.data, starts.ctypes.data,
+                             sizes.ctypes.data, mask_words.ctypes.data, arrivals.ctypes.data, n,
+                             threads, masks.ctypes.data, counts.ctypes.data, tickets.ctypes.data,
+                             submit.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("ace_verify_stream failed (%d)" % rc)
+    return tickets, submit, masks, mask_words, counts
 
 
 @dataclasses.dataclass

@@ -186,3 +186,30 @@ def test_empty_request_and_bad_ticket(ace, pool):
     from paper_2603_10242_amd.ace import load
     assert load().ace_stream_poll(s._h, 999_999, 0) == ace.ACE_ERR_INVALID_ARG
     s.close()
+
+
+def test_native_open_loop_driver(ace, pool):
+    """The serving benchmark's native load generator submits every request at
+    its arrival time through ace_verify_stream; each result matches the truth."""
+    import ctypes
+    import time
+    st = ace.Stream.create_host(oracle_verify(pool.keys), 64 << 20, 16 << 20, max_inflight=4)
+    try:
+        r = np.random.Generator(np.random.PCG64(17))
+        sizes = r.integers(1, 1500, size=120).astype(np.uint64)
+        starts = r.integers(0, pool.n - 1500, size=120).astype(np.uint64)
+        arrivals = time.monotonic() + 0.02 + np.cumsum(r.exponential(2e-4, size=120))
+        fn = ctypes.cast(ace.load().ace_verify_stream, ctypes.c_void_p).value
+        tickets, submit, masks, mask_words, counts = W.client_drive(
+            fn, st._h.value, pool, starts, sizes, arrivals, threads=3)
+        assert (submit >= arrivals - 1e-4).all()          # nobody submits before arrival
+        for k in range(120):
+            t = ace.Ticket(int(tickets[k]), int(sizes[k]), None, None)
+            st.poll(t, True)
+            lo, n = int(starts[k]), int(sizes[k])
+            w0 = int(mask_words[k])
+            assert int(counts[k]) == int(pool.truth[lo:lo + n].sum())
+            assert np.array_equal(masks[w0:w0 + (n + 31) // 32], W.pack_bits(pool.truth[lo:lo + n]))
+            st.release(t)
+    finally:
+        st.close()
