@@ -103,14 +103,6 @@ def cpu_baseline(w, seconds: float) -> dict:
     if sample % 32 == 0 and not np.array_equal(mask, truth):
         raise SystemExit("oracle disagrees with the generator's truth mask")
     step_s = t_derive + t_verify * (w.n / sample)
-    # context: the same HMAC check with OpenSSL's EVP_MAC (an optimized CPU library), all cores
-    from paper_2603_10242_amd import workload as W
-    t = time.perf_counter()
-    ossl = W.client_sign(keys, w.msg, w.off[: sample + 1], w.ids[:sample], threads)
-    t_ossl = time.perf_counter() - t
-    if sample % 32 == 0 and not np.array_equal(
-            W.pack_bits(np.all(ossl == w.tags[:sample], axis=1)), mask):
-        raise SystemExit("OpenSSL and the oracle disagree")
     # one thread, for the per-transaction cost the paper quotes for one core
     one = min(w.n, 50_000)
     t = time.perf_counter()
@@ -121,7 +113,6 @@ def cpu_baseline(w, seconds: float) -> dict:
                       "(%.2f s), verify time scaled to the whole batch" %
                       (w.n_id, t_derive, sample, w.n, t_verify),
             "single_thread_us_per_tx": us_per_tx_1t,
-            "openssl_hmac_per_s": sample / t_ossl,
             "host_cpu": host_cpu_model()}
 
 
@@ -536,6 +527,65 @@ def bench_merkle(args) -> dict:
     }
 
 
+def bench_derive(args) -> dict:
+    """Key derivation: one stream (the attestation keys of 1M identities) and
+    the seven purpose streams of Def. 2.1 plus the two validator streams for
+    the same identities in one call."""
+    from paper_2603_10242_amd import workload as W
+    import torch
+    from paper_2603_10242_amd import ace
+    ace.load()
+    torch.cuda.set_device(0)
+    n = args.n_id
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([W.SEED_BASE + 9])))
+    rev_h = rng.integers(0, 256, size=(n, 32), dtype=np.uint8)
+    rev = ace.to_device(rev_h)
+    salt = rng.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+    infos = [b"ACEGF-V1-ED25519-SOLANA", b"ACEGF-V1-ED25519-POLKADOT", b"ACEGF-V1-SECP256K1-EVM",
+             b"ACEGF-V1-SECP256K1-BTC", b"ACEGF-V1-SECP256K1-COSMOS", b"ACEGF-V1-X25519-IDENTITY",
+             b"ACEGF-V1-ML-DSA-44-PQC-IDENTITY", b"ACEGF-V1-VALIDATOR-CONSENSUS",
+             b"ACEGF-V1-VALIDATOR-VOTE"]
+    streams = [(salt, i) for i in infos]
+    mid = torch.empty((n, 16), dtype=torch.int32, device="cuda")
+    keys = torch.empty((len(streams), n, 32), dtype=torch.uint8, device="cuda")
+    # correctness on a sample of identities against the client's OpenSSL HKDF
+    ace.derive_keys_multi(rev, streams, key_out=keys)
+    torch.cuda.synchronize()
+    sample = np.arange(0, n, max(1, n // 512))
+    for sidx, (sa, inf) in enumerate(streams):
+        want = W.client_keys(rev_h[sample], sa, inf)
+        if not np.array_equal(keys[sidx].cpu().numpy()[sample], want):
+            raise SystemExit("RESULT MISMATCH in stream %d" % sidx)
+    log("keys of %d sampled identities in %d streams equal OpenSSL's" % (sample.size, len(streams)))
+    ms1, ev1 = time_calls(lambda: ace.derive_keys(rev, salt, W.INFO_ATTEST, mid_out=mid),
+                          args.steps, args.warmup)
+    msm, evm = time_calls(lambda: ace.derive_keys_multi(rev, streams, key_out=keys), args.steps,
+                          args.warmup)
+    c1 = 8 * n + 2
+    cm = len(streams) * (8 * n + 2)
+    f1 = c1 * I_REF / (np.median(ev1) / 1e3) / 1e12 / PEAK_INT32_TOPS
+    fm = cm * I_REF / (np.median(evm) / 1e3) / 1e12 / PEAK_INT32_TOPS
+    log("one stream: %.3f ms (%.1f%% of peak); %d streams: %.3f ms (%.1f%% of peak)"
+        % (np.median(ev1), 100 * f1, len(streams), np.median(evm), 100 * fm))
+    return {
+        "metric": "derived HKDF keys/sec on 1 GPU; %peak INT32 VALU",
+        "value": len(streams) * n / (msm / 1e3), "unit": "keys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": msm,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "HKDF keys: %d identities x %d purpose streams" % (n, len(streams)),
+                   "identities": n, "streams": len(streams)},
+        "roofline": {"kernel": "k_derive_multi", "bound": "alu", "achieved": fm * PEAK_INT32_TOPS,
+                     "peak": PEAK_INT32_TOPS, "unit": "T int32 lane-instr/s", "frac": fm,
+                     "traffic": None, "per_launch": "%d compressions x %d VALU instr" % (cm, I_REF),
+                     "avg_ms": float(np.median(evm))},
+        "one_stream": {"ms": float(np.median(ev1)), "keys_per_s": n / (np.median(ev1) / 1e3),
+                       "frac": f1, "outputs": "midstates"},
+        "per_identity_all_streams_ns": float(np.median(evm)) * 1e6 / n,
+        "device": torch.cuda.get_device_name(0),
+    }
+
+
 def bench_sweep_table(args) -> dict:
     """The throughput sweep's grid: n = 1..16M transactions, resident midstates
     against keys derived in the step, the per-transaction derivation ablation,
@@ -608,12 +658,13 @@ def main() -> int:
                     help="derive every identity's key in the step, or use resident midstates")
     ap.add_argument("--mode", choices=["binned", "binned-persistent", "ordered"], default="binned")
     ap.add_argument("--workload", choices=["sweep", "batching", "serving", "sweep-table",
-                                           "attest", "poh", "merkle"],
+                                           "attest", "poh", "merkle", "derive"],
                     default="sweep",
                     help="sweep: the throughput sweep (default); batching: 256 uneven blocks; "
                          "serving: Poisson requests through the serving engine; "
                          "attest: paper-form attestations with payload binding; "
-                         "poh: hash-chain segment verification; merkle: attestation roots")
+                         "poh: hash-chain segment verification; merkle: attestation roots; "
+                         "derive: HKDF key streams")
     ap.add_argument("--poh-segments", type=int, default=1 << 18)
     ap.add_argument("--poh-steps", type=int, default=1024)
     ap.add_argument("--pool", type=int, default=4 << 20, help="serving: transactions in the pool")
@@ -644,6 +695,9 @@ def main() -> int:
         return 0
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return 0
+    if args.workload == "derive":
+        print(json.dumps(bench_derive(args)), flush=True)
         return 0
     if args.workload == "merkle":
         print(json.dumps(bench_merkle(args)), flush=True)

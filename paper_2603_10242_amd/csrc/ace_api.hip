@@ -728,7 +728,7 @@ ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, voi
         if ((rc = launch_status("k_merkle_leaves launch"))) return rc;
     }
     if (p.levels) {
-        hipLaunchKernelGGL(k_merkle_plan, dim3(1), dim3(kPlanThreads), 0, s, table, n_trees, p.levels, P);
+        hipLaunchKernelGGL(k_merkle_plan, dim3(p.levels), dim3(kPlanThreads), 0, s, table, n_trees, P);
         if ((rc = launch_status("k_merkle_plan launch"))) return rc;
     }
     for (uint32_t k = 0; k < p.levels; ++k) {

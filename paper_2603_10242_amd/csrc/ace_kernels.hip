@@ -185,73 +185,66 @@ __device__ void hkdf_prepare(const Params &hp, HkdfPrep &out)
     }
 }
 
+// HMAC midstates F(IV, K0 ^ ipad) and F(IV, K0 ^ opad) of a 32-byte key held
+// as state words (K0 = key || 0^32): one call site, two passes.
+__device__ __forceinline__ void hmac_midstates(const State &k, State &ipad, State &opad)
+{
+#pragma nounroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint32_t pad = pass ? 0x5c5c5c5cu : 0x36363636u;
+        uint32_t W[16];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) W[i] = k.h[i] ^ pad;
+#pragma unroll
+        for (int i = 8; i < 16; ++i) W[i] = pad;
+        State t = initial_state();
+        compress_block(t, W);
+        if (pass) opad = t;
+        else ipad = t;
+    }
+}
+
+// F(in, m || 0x80 || 0 || 768): a 32-byte message after a 64-byte key block.
+__device__ __forceinline__ void compress_tail32(State &in, const State &m)
+{
+    uint32_t W[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) W[i] = m.h[i];
+    W[8] = 0x80000000u;
+#pragma unroll
+    for (int i = 9; i < 15; ++i) W[i] = 0u;
+    W[15] = 768u;
+    compress_block(in, W);
+}
+
 // HKDF-SHA256 (RFC 5869, L = 32) of one 32-byte root entropy rv (big-endian
-// words) and the midstates of the resulting key, as one loop over a single
-// compression body (keeps the code small enough for the instruction cache):
-//   0 inner extract   F(salt_ipad, rv || pad)
-//   1 PRK             F(salt_opad, inner || pad)
-//   2,3               PRK midstates F(IV, PRK^ipad), F(IV, PRK^opad)
-//   4 .. 3+nq         expand inner over info || 0x01 from the PRK ipad state
-//   4+nq  key k       F(PRK opad state, inner || pad)
-//   5+nq, 6+nq        key midstates F(IV, k^ipad), F(IV, k^opad)
+// words) and the midstates of the resulting key:
+//   extract  PRK = HMAC(salt, rv): F(salt_ipad, rv || pad), then F(salt_opad, . || pad)
+//   expand   k = HMAC(PRK, info || 0x01): PRK midstates, the info blocks from
+//            the PRK ipad state, then F(PRK opad state, . || pad)
+//   and the key's own midstates F(IV, k^ipad), F(IV, k^opad).
 __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], const HkdfPrep &P,
                                             uint32_t (&key)[8], State &kip, State &kop)
 {
+    (void)live;  // lanes without an identity compute on zeros; their results are not stored
+    State m, x, prk;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { m.h[i] = rv[i]; x.h[i] = P.salt_ipad[i]; prk.h[i] = P.salt_opad[i]; }
+    compress_tail32(x, m);
+    compress_tail32(prk, x);
+    State pi, po;
+    hmac_midstates(prk, pi, po);
     const uint32_t nq = P.info_blocks;
-    const uint32_t nsteps = 7 + nq;
-    State x, A, B;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) { x.h[i] = 0; A.h[i] = 0; B.h[i] = 0; }
-    for (uint32_t s = 0; s < nsteps; ++s) {
+    for (uint32_t q = 0; q < nq; ++q) {
         uint32_t W[16];
-        State in;
-        if (s == 0 || s == 1 || s == 4 + nq) {
-            // 32-byte message after a key block: words 8..15 are fixed
-            if (s == 0) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) { in.h[i] = P.salt_ipad[i]; W[i] = rv[i]; }
-            } else if (s == 1) {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) { in.h[i] = P.salt_opad[i]; W[i] = x.h[i]; }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) { in.h[i] = A.h[i]; W[i] = x.h[i]; }
-            }
-            W[8] = 0x80000000u;
-#pragma unroll
-            for (int i = 9; i < 15; ++i) W[i] = 0;
-            W[15] = 768u;
-        } else if (s == 2 || s == 3 || s == 5 + nq || s == 6 + nq) {
-            // key midstates: the key is A (PRK or k) after the move below
-            if (s == 2 || s == 5 + nq) A = x;
-            else B = x;
-            const uint32_t pad = (s == 2 || s == 5 + nq) ? 0x36363636u : 0x5c5c5c5cu;
-            in = initial_state();
-#pragma unroll
-            for (int i = 0; i < 8; ++i) W[i] = A.h[i] ^ pad;
-#pragma unroll
-            for (int i = 8; i < 16; ++i) W[i] = pad;
-        } else {
-            // expand blocks: first one starts from the PRK ipad state (B)
-            if (s == 4) {
-                const State pi = B;
-                A = x;   // PRK opad state, needed at step 4 + nq
-                in = pi;
-            } else {
-                in = x;
-            }
-            const uint32_t q = s - 4;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
-        }
-        if (live) compress_block(in, W);
-        x = in;
+        for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
+        compress_block(pi, W);
     }
-    // after the loop: A = k, B = F(IV, k^ipad), x = F(IV, k^opad)
+    compress_tail32(po, pi);  // po = k
 #pragma unroll
-    for (int i = 0; i < 8; ++i) key[i] = A.h[i];
-    kip = B;
-    kop = x;
+    for (int i = 0; i < 8; ++i) key[i] = po.h[i];
+    hmac_midstates(po, kip, kop);
 }
 
 // ------------------------------------------------------------------------------------------

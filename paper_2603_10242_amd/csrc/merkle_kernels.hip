@@ -13,7 +13,8 @@
 // level expects it.
 //
 //   k_merkle_leaves  one leaf per lane: SHA-256 of its bytes into its slot.
-//   k_merkle_plan    per level, exclusive prefix of each tree's pair count.
+//   k_merkle_plan    per level (one workgroup each), exclusive prefix of each
+//                    tree's pair count.
 //   k_merkle_level   one parent per lane at level k -> k + 1 (two blocks:
 //                    the 64 child bytes, then the constant padding block).
 //   k_merkle_out     roots to the callers' 32-byte outputs.
@@ -35,6 +36,44 @@ struct MerkleChunk {
     uint32_t count;
 };
 
+// The second block of every parent is the padding of a 64-byte message
+// (0x80, zeros, bit length 512): its whole message schedule is known at
+// compile time, so it is folded into the round constants, kw[t] = K[t] +
+// W[t], and the block costs the 64 rounds and the feed-forward only.
+constexpr uint32_t c_rotr(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
+struct ScheduleKW {
+    uint32_t v[64];
+};
+constexpr ScheduleKW fold_pad64()
+{
+    ScheduleKW r{};
+    uint32_t w[64] = {};
+    w[0] = 0x80000000u;
+    w[15] = 512u;
+    for (int t = 16; t < 64; ++t) {
+        const uint32_t s0 = c_rotr(w[t - 15], 7) ^ c_rotr(w[t - 15], 18) ^ (w[t - 15] >> 3);
+        const uint32_t s1 = c_rotr(w[t - 2], 17) ^ c_rotr(w[t - 2], 19) ^ (w[t - 2] >> 10);
+        w[t] = s1 + w[t - 7] + s0 + w[t - 16];
+    }
+    for (int t = 0; t < 64; ++t) r.v[t] = kRound[t] + w[t];
+    return r;
+}
+__constant__ __attribute__((aligned(64))) ScheduleKW kPad64KW = fold_pad64();
+
+__device__ __forceinline__ void compress_pad64(State &s)
+{
+    uint32_t a = s.h[0], b = s.h[1], c = s.h[2], d = s.h[3];
+    uint32_t e = s.h[4], f = s.h[5], g = s.h[6], h = s.h[7];
+#pragma nounroll
+    for (int q = 0; q < 4; ++q) {
+        const RoundConsts16 kq = *reinterpret_cast<const RoundConsts16 *>(&kPad64KW.v[16 * q]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) round_step(a, b, c, d, e, f, g, h, 0u, kq.k[j]);
+    }
+    s.h[0] += a; s.h[1] += b; s.h[2] += c; s.h[3] += d;
+    s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
+}
+
 __global__ void k_merkle_put(MerkleDesc *table, MerkleChunk c)
 {
     const uint32_t t = threadIdx.x;
@@ -55,10 +94,13 @@ __device__ __forceinline__ uint32_t merkle_tree_of(const MerkleDesc *table, uint
     return lo;
 }
 
-// SHA-256 of L bytes at p into S (from the initial value).  Every dword
-// address is clamped to one that holds message bytes (for L == 0 none is
-// read), so nothing outside the leaf's bytes is touched.
-__device__ __forceinline__ void sha256_bytes(bool live, const uint8_t *p, uint64_t L, State &S)
+// SHA-256 of L bytes at p into S (from the initial value).  With
+// overread_ok (the tree's data area extends at least 80 bytes past this
+// leaf) whole 16-byte loads are used, whose bytes past the leaf's end feed
+// only words the padding overwrites; otherwise every dword address is
+// clamped to one that holds leaf bytes (for L == 0 none is read).
+__device__ __forceinline__ void sha256_bytes(bool live, const uint8_t *p, uint64_t L, State &S,
+                                             bool overread_ok = false)
 {
     S = initial_state();
     const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;
@@ -74,10 +116,20 @@ __device__ __forceinline__ void sha256_bytes(bool live, const uint8_t *p, uint64
         if (__ballot(run) == 0) break;
         if (run) {
             uint32_t D[17], W[16];
+            if (overread_ok) {
+                const uint32_t *q = A0 + 16ull * b;
+                const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
+                D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
+                D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
+                D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
+                D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
+                D[16] = load32(q + 16);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 17; ++k) {
-                const uint64_t idx = 16ull * b + k;
-                D[k] = lim ? A0[idx < last ? idx : last] : 0u;
+                for (int k = 0; k < 17; ++k) {
+                    const uint64_t idx = 16ull * b + k;
+                    D[k] = lim ? load32(A0 + (idx < last ? idx : last)) : 0u;
+                }
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
@@ -111,15 +163,19 @@ __global__ void __launch_bounds__(kWG) k_merkle_leaves(const MerkleDesc *__restr
     const bool live = g < n_leaves;
     const uint8_t *p = nullptr;
     uint64_t L = 0;
+    bool overread_ok = false;
     if (live) {
         const MerkleDesc d = table[merkle_tree_of(table, n_trees, g)];
         const uint64_t i = g - d.leaf0;
         const uint64_t a = d.off[i], e = d.off[i + 1];
         p = d.data + a;
         L = e >= a ? e - a : 0;  // decreasing offsets: the empty leaf
+        // 17 dwords from the aligned start of the last block reach at most 76
+        // bytes past the leaf's end; the tree's leaves end at off[n]
+        overread_ok = e >= a && a + L + 80 <= d.off[d.n];
     }
     State S;
-    sha256_bytes(live, p, L, S);
+    sha256_bytes(live, p, L, S, overread_ok);
     if (live) {
         uint32_t *q = nodes + 8ull * g;
 #pragma unroll
@@ -128,40 +184,39 @@ __global__ void __launch_bounds__(kWG) k_merkle_leaves(const MerkleDesc *__restr
 }
 
 // P[k * (n_trees + 1) + b] = pairs at level k of trees before b; the last
-// entry of each row is the level's total.  One workgroup of kPlanThreads.
+// entry of each row is the level's total.  Workgroup k scans level k.
 constexpr uint32_t kPlanThreads = 1024;
 __global__ void __launch_bounds__(kPlanThreads) k_merkle_plan(const MerkleDesc *__restrict__ table,
-                                                              uint32_t n_trees, uint32_t levels,
+                                                              uint32_t n_trees,
                                                               unsigned long long *__restrict__ P)
 {
     __shared__ unsigned long long part[kPlanThreads];
     const uint32_t t = threadIdx.x;
-    for (uint32_t k = 0; k < levels; ++k) {
-        unsigned long long *row = P + (uint64_t)k * (n_trees + 1);
-        unsigned long long running = 0;
-        for (uint32_t c = 0; c < n_trees; c += kPlanThreads) {
-            const uint32_t b = c + t;
-            unsigned long long v = 0;
-            if (b < n_trees) {
-                const uint64_t n = table[b].n;
-                const uint64_t m = k >= 63 ? (n ? 1 : 0) : (n + (1ull << k) - 1) >> k;
-                v = m >> 1;
-            }
-            part[t] = v;
+    const uint32_t k = blockIdx.x;
+    unsigned long long *row = P + (uint64_t)k * (n_trees + 1);
+    unsigned long long running = 0;
+    for (uint32_t c = 0; c < n_trees; c += kPlanThreads) {
+        const uint32_t b = c + t;
+        unsigned long long v = 0;
+        if (b < n_trees) {
+            const uint64_t n = table[b].n;
+            const uint64_t m = k >= 63 ? (n ? 1 : 0) : (n + (1ull << k) - 1) >> k;
+            v = m >> 1;
+        }
+        part[t] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan
+        for (uint32_t s = 1; s < kPlanThreads; s <<= 1) {
+            const unsigned long long add = t >= s ? part[t - s] : 0ull;
             __syncthreads();
-            // Hillis-Steele inclusive scan
-            for (uint32_t s = 1; s < kPlanThreads; s <<= 1) {
-                const unsigned long long add = t >= s ? part[t - s] : 0ull;
-                __syncthreads();
-                part[t] += add;
-                __syncthreads();
-            }
-            if (b < n_trees) row[b] = running + part[t] - v;
-            running += part[kPlanThreads - 1];
+            part[t] += add;
             __syncthreads();
         }
-        if (t == 0) row[n_trees] = running;
+        if (b < n_trees) row[b] = running + part[t] - v;
+        running += part[kPlanThreads - 1];
+        __syncthreads();
     }
+    if (t == 0) row[n_trees] = running;
 }
 
 __global__ void __launch_bounds__(kWG) k_merkle_level(const MerkleDesc *__restrict__ table,
@@ -198,12 +253,7 @@ __global__ void __launch_bounds__(kWG) k_merkle_level(const MerkleDesc *__restri
     if (__ballot(live) == 0) return;
     State S = initial_state();
     compress_block(S, W);
-    // the 64-byte message's padding block: 0x80, zeros, bit length 512
-    W[0] = 0x80000000u;
-#pragma unroll
-    for (int j = 1; j < 15; ++j) W[j] = 0u;
-    W[15] = 512u;
-    compress_block(S, W);
+    compress_pad64(S);  // the 64-byte message's padding block
     if (live) {
         uint32_t *o = nodes + 8ull * left;
 #pragma unroll
