@@ -205,13 +205,18 @@ ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blo
  *   aux_wgs_per_cu     workgroups per CU of the binning and finalize passes
  *   auto_persistent    1: binned batches in the open mode use the persistent
  *                      verify kernel
- * ace_set_tuning rejects workgroup counts outside 1..64.
+ *   derive_wgs_per_cu  workgroups per CU of the key derivation while it runs
+ *                      beside the binning passes (keys derived in a binned
+ *                      call); 0: one workgroup per 256 identities
+ * ace_set_tuning rejects workgroup counts outside 1..64 (derive_wgs_per_cu:
+ * 0..64).
  */
 typedef struct {
     uint64_t binned_min_tx;
     uint32_t verify_wgs_per_cu;
     uint32_t aux_wgs_per_cu;
     uint32_t auto_persistent;
+    uint32_t derive_wgs_per_cu;
 } ace_tuning;
 
 ACE_API int ace_get_tuning(ace_tuning *out);

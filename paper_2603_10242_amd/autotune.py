@@ -9,7 +9,9 @@ installs the fastest through ace_set_tuning:
 * verify_wgs_per_cu ("tiles per CU"): workgroups per CU of the persistent
   verify kernel (and of the graph's in-order one), and whether the open mode
   should use the persistent kernel at all (auto_persistent);
-* aux_wgs_per_cu: workgroups per CU of the binning and finalize passes.
+* aux_wgs_per_cu: workgroups per CU of the binning and finalize passes;
+* derive_wgs_per_cu: workgroups per CU of the key derivation while it runs on
+  a second stream beside the binning passes (fewer leave room for them).
 
 One transaction always owns one lane: SHA-256 is a Merkle-Damgard chain, so
 the blocks of one message cannot be split across lanes, and the candidates
@@ -146,8 +148,22 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
         if t < best_aux[0]:
             best_aux = (t, apc)
 
+    # 4. key derivation beside the binning passes (keys derived in the call):
+    # workgroups per CU, 0 = one workgroup per 256 identities
+    ace.set_tuning(aux_wgs_per_cu=int(best_aux[1]))
+    rks = ace.rev_keyset(ace.to_device(w.rev), w.salt, w.info)
+    best_der = (float("inf"), default.get("derive_wgs_per_cu", 1))
+    for dpc in (0, 1, 2, 4):
+        ace.set_tuning(derive_wgs_per_cu=dpc)
+        t = _time(lambda: ace.verify_batch(rks, [blk], flags=ace.ACE_BUCKETED))
+        meas.append({"n": big, "n_id": int(w.n_id), "derive_wgs_per_cu": dpc, "ms": t})
+        log("derive %2d WG/CU beside binning: %.3f ms" % (dpc, t))
+        if t < best_der[0]:
+            best_der = (t, dpc)
+
     tuning = {"binned_min_tx": int(binned_min), "verify_wgs_per_cu": int(best_wpc),
-              "aux_wgs_per_cu": int(best_aux[1]), "auto_persistent": int(best[2])}
+              "aux_wgs_per_cu": int(best_aux[1]), "auto_persistent": int(best[2]),
+              "derive_wgs_per_cu": int(best_der[1])}
     ace.set_tuning(**tuning)
     result = {"arch": arch, "cus": cus, "tuning": tuning, "lanes_per_message": 1,
               "measured": meas, "when": time.strftime("%Y-%m-%d %H:%M:%S")}

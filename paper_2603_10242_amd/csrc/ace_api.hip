@@ -17,6 +17,7 @@
 // The kernels are compiled in this translation unit.
 #include "ace_kernels.hip"
 #include "valu_rate.hip"
+#include "chain_kernels.hip"
 #include "merkle_kernels.hip"
 
 using namespace ace;
@@ -74,6 +75,7 @@ ace_tuning g_tune = {
     /* verify_wgs_per_cu */ 8,
     /* aux_wgs_per_cu    */ 8,
     /* auto_persistent   */ 0,
+    /* derive_wgs_per_cu */ 1,
 };
 
 ace_tuning tuning()
@@ -377,13 +379,15 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     } else {
         uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
         if (keys->n_id) {
-            const unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
+            unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
             hipStream_t ds = s;
             if (binned && (graph || p.total_tx) && (fk = fork_ctx())) {
                 if ((rc = check_hip(hipEventRecord(fk->fork, s), "hipEventRecord"))) return rc;
                 if ((rc = check_hip(hipStreamWaitEvent(fk->aux, fk->fork, 0), "hipStreamWaitEvent")))
                     return rc;
                 ds = fk->aux;
+                // leave wave slots to the binning passes on the caller's stream
+                if (tn.derive_wgs_per_cu) g = std::min<unsigned>(g, tn.derive_wgs_per_cu * cus);
             }
             hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, ds, keys->d_rev, keys->n_id,
                                (uint8_t *)nullptr, mid, hp);
@@ -544,8 +548,8 @@ ACE_API int ace_set_tuning(const ace_tuning *t)
     clear_error();
     if (!t) return fail(ACE_ERR_INVALID_ARG, "tuning is NULL");
     if (t->verify_wgs_per_cu < 1 || t->verify_wgs_per_cu > 64 || t->aux_wgs_per_cu < 1 ||
-        t->aux_wgs_per_cu > 64)
-        return fail(ACE_ERR_INVALID_ARG, "workgroups per CU must be in 1..64");
+        t->aux_wgs_per_cu > 64 || t->derive_wgs_per_cu > 64)
+        return fail(ACE_ERR_INVALID_ARG, "workgroups per CU must be in 1..64 (derive: 0..64)");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune = *t;
     return ACE_OK;

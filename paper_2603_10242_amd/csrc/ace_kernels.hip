@@ -1,16 +1,19 @@
 // ace_kernels.hip -- gfx950 kernels of the attestation check.
 //
-//   k_derive         HKDF-SHA256 per identity (Def. 2.1 / equation attestkey)
-//                    and the HMAC midstates of the derived key.
 //   k_zero           clears the per-block counts and the binning control words.
 //   k_bin_count      histogram of transactions by inner block count.
 //   k_bin_scan       bin start positions, longest messages first.
-//   k_bin_scatter    transaction indices into bin order.
+//   k_bin_scatter    transaction records into bin order.
 //   k_verify         Alg. 1 Phase 1a per transaction: inner hash of the message
 //                    from the cached ipad midstate, outer hash from the opad
 //                    midstate, constant-time compare with the credential,
-//                    wave64 ballot of the verdicts.
-//   k_finalize       bin-order verdicts back to input order; per-block counts.
+//                    wave64 ballot of the verdicts (also the paper's
+//                    attestation form, Def. 3.1 with Alg. 2's payload binding).
+//   k_finalize       bin-order verdicts back to input order.
+//   k_count          valid counts from the finished bitmasks.
+//   k_plan           device-side plan of a graph replay.
+// The key derivation (Def. 2.1) is in hkdf_kernels.hip, the hash-chain
+// segments in chain_kernels.hip, the Merkle roots in merkle_kernels.hip.
 //
 // One transaction per lane.  Message bytes are read straight from HBM as
 // aligned dwords and turned into big-endian schedule words with one
@@ -103,212 +106,11 @@ __device__ __forceinline__ uint32_t find_block(const Batch &bt, const Totals &T,
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Big-endian word g of the SHA-256 padding of the byte string
-// p[0..len) || tail[0..tail_len) whose bit-length field holds `bitlen` and
-// whose padded form has `nblocks` blocks (FIPS 180-4 sec. 5.1.1).
-__device__ inline uint32_t padded_word(const uint8_t *p, uint32_t len, uint32_t tail,
-                                       uint32_t tail_len, uint32_t g, uint32_t nblocks,
-                                       uint64_t bitlen)
-{
-    if (g == 16 * nblocks - 2) return (uint32_t)(bitlen >> 32);
-    if (g == 16 * nblocks - 1) return (uint32_t)bitlen;
-    const uint32_t total = len + tail_len;
-    uint32_t w = 0;
-    for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t pos = 4 * g + k;
-        uint32_t byte;
-        if (pos < len) byte = p[pos];
-        else if (pos < total) byte = (tail >> (8 * (pos - len))) & 0xFFu;
-        else byte = pos == total ? 0x80u : 0u;
-        w = (w << 8) | byte;
-    }
-    return w;
-}
+}  // namespace ace
 
-// Per-workgroup HKDF constants: the salt's HMAC midstates and the padded
-// expand input (info || 0x01), built by wave 0 (all lanes compute the same
-// values) into LDS.
-template <class Params>
-__device__ void hkdf_prepare(const Params &hp, HkdfPrep &out)
-{
-    uint32_t k0[16];
-    const uint32_t sl = hp.salt_len;
-    if (sl > 64) {
-        // RFC 2104: keys longer than the block are hashed first.
-        const uint32_t nblk = (sl + 9 + 63) / 64;
-        State s = initial_state();
-        for (uint32_t blk = 0; blk < nblk; ++blk) {
-            uint32_t W[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) W[j] = padded_word(hp.salt, sl, 0, 0, 16 * blk + j, nblk, 8ull * sl);
-            compress(s, W);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) k0[j] = s.h[j];
-#pragma unroll
-        for (int j = 8; j < 16; ++j) k0[j] = 0;
-    } else {
-        // RFC 5869: an absent salt is HashLen zero bytes, whose key block is
-        // the same all-zero K0 as the empty key's.
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            uint32_t w = 0;
-            for (uint32_t k = 0; k < 4; ++k) {
-                const uint32_t pos = 4 * j + k;
-                w = (w << 8) | (pos < sl ? hp.salt[pos] : 0u);
-            }
-            k0[j] = w;
-        }
-    }
-    for (int pass = 0; pass < 2; ++pass) {
-        const uint32_t x = pass ? 0x5c5c5c5cu : 0x36363636u;
-        uint32_t W[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) W[j] = k0[j] ^ x;
-        State s = initial_state();
-        compress(s, W);
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) (pass ? out.salt_opad : out.salt_ipad)[j] = s.h[j];
-        }
-    }
-    // Expand input T(1) = HMAC(PRK, info || 0x01): after the 64-byte key
-    // block the hashed stream is info || 0x01, bit length (64 + len + 1) * 8.
-    const uint32_t il = hp.info_len;
-    const uint32_t nq = (il + 1 + 9 + 63) / 64;
-    if (lane_id() == 0) {
-        for (uint32_t q = 0; q < nq; ++q)
-            for (uint32_t j = 0; j < 16; ++j)
-                out.info_words[q][j] =
-                    padded_word(hp.info, il, 0x01u, 1, 16 * q + j, nq, 8ull * (64 + il + 1));
-        out.info_blocks = nq;
-    }
-}
+#include "hkdf_kernels.hip"
 
-// HMAC midstates F(IV, K0 ^ ipad) and F(IV, K0 ^ opad) of a 32-byte key held
-// as state words (K0 = key || 0^32): one call site, two passes.
-__device__ __forceinline__ void hmac_midstates(const State &k, State &ipad, State &opad)
-{
-#pragma nounroll
-    for (int pass = 0; pass < 2; ++pass) {
-        const uint32_t pad = pass ? 0x5c5c5c5cu : 0x36363636u;
-        uint32_t W[16];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) W[i] = k.h[i] ^ pad;
-#pragma unroll
-        for (int i = 8; i < 16; ++i) W[i] = pad;
-        State t = initial_state();
-        compress_block(t, W);
-        if (pass) opad = t;
-        else ipad = t;
-    }
-}
-
-// F(in, m || 0x80 || 0 || 768): a 32-byte message after a 64-byte key block.
-__device__ __forceinline__ void compress_tail32(State &in, const State &m)
-{
-    uint32_t W[16];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) W[i] = m.h[i];
-    W[8] = 0x80000000u;
-#pragma unroll
-    for (int i = 9; i < 15; ++i) W[i] = 0u;
-    W[15] = 768u;
-    compress_block(in, W);
-}
-
-// HKDF-SHA256 (RFC 5869, L = 32) of one 32-byte root entropy rv (big-endian
-// words) and the midstates of the resulting key:
-//   extract  PRK = HMAC(salt, rv): F(salt_ipad, rv || pad), then F(salt_opad, . || pad)
-//   expand   k = HMAC(PRK, info || 0x01): PRK midstates, the info blocks from
-//            the PRK ipad state, then F(PRK opad state, . || pad)
-//   and the key's own midstates F(IV, k^ipad), F(IV, k^opad).
-__device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], const HkdfPrep &P,
-                                            uint32_t (&key)[8], State &kip, State &kop)
-{
-    (void)live;  // lanes without an identity compute on zeros; their results are not stored
-    State m, x, prk;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) { m.h[i] = rv[i]; x.h[i] = P.salt_ipad[i]; prk.h[i] = P.salt_opad[i]; }
-    compress_tail32(x, m);
-    compress_tail32(prk, x);
-    State pi, po;
-    hmac_midstates(prk, pi, po);
-    const uint32_t nq = P.info_blocks;
-    for (uint32_t q = 0; q < nq; ++q) {
-        uint32_t W[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
-        compress_block(pi, W);
-    }
-    compress_tail32(po, pi);  // po = k
-#pragma unroll
-    for (int i = 0; i < 8; ++i) key[i] = po.h[i];
-    hmac_midstates(po, kip, kop);
-}
-
-// ------------------------------------------------------------------------------------------
-// k_derive: one identity per lane.
-// ------------------------------------------------------------------------------------------
-// Key and midstates of identity j under the prepared parameter set; outputs
-// go to row `row` of key_out / mid_out.
-__device__ __forceinline__ void derive_identity(const uint8_t *__restrict__ rev, uint32_t n_id,
-                                                uint32_t j, uint64_t row, const HkdfPrep &prep,
-                                                uint8_t *__restrict__ key_out,
-                                                uint32_t *__restrict__ mid_out)
-{
-    const bool live = j < n_id;
-    uint32_t rv[8];
-    if (live) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(rev + 32ull * j);
-        const U4 a = load16(p), b = load16(p + 4);
-        rv[0] = bswap32(a.x); rv[1] = bswap32(a.y); rv[2] = bswap32(a.z); rv[3] = bswap32(a.w);
-        rv[4] = bswap32(b.x); rv[5] = bswap32(b.y); rv[6] = bswap32(b.z); rv[7] = bswap32(b.w);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) rv[i] = 0;
-    }
-    uint32_t key[8];
-    State kip, kop;
-    derive_lane(live, rv, prep, key, kip, kop);
-    if (!live) return;
-    if (key_out) {
-        uint32_t *q = reinterpret_cast<uint32_t *>(key_out + 32ull * row);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) q[i] = bswap32(key[i]);
-    }
-    if (mid_out) {
-        uint32_t *q = mid_out + 16ull * row;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) { q[i] = kip.h[i]; q[8 + i] = kop.h[i]; }
-    }
-}
-
-__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__restrict__ rev, uint32_t n_id,
-                                                uint8_t *__restrict__ key_out,
-                                                uint32_t *__restrict__ mid_out, HkdfParams hp)
-{
-    __shared__ HkdfPrep prep;
-    if (threadIdx.x < 64) hkdf_prepare(hp, prep);
-    __syncthreads();
-    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
-    derive_identity(rev, n_id, j, j, prep, key_out, mid_out);
-}
-
-// k_derive_multi: grid row y derives every identity's key under parameter set
-// first + y (Def. 2.1's purpose streams, per-slot domains); output row
-// (first + y) * n_id + j.
-__global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive_multi(const uint8_t *__restrict__ rev,
-                                                      uint32_t n_id, uint8_t *__restrict__ key_out,
-                                                      uint32_t *__restrict__ mid_out, MultiHkdf mp)
-{
-    __shared__ HkdfPrep prep;
-    const uint32_t y = blockIdx.y;
-    if (threadIdx.x < 64) hkdf_prepare(mp.s[y], prep);
-    __syncthreads();
-    const uint32_t j = blockIdx.x * kWG + threadIdx.x;
-    derive_identity(rev, n_id, j, (uint64_t)(mp.first + y) * n_id + j, prep, key_out, mid_out);
-}
+namespace ace {
 
 // ------------------------------------------------------------------------------------------
 // Verification of one transaction per lane.
@@ -910,73 +712,6 @@ __global__ void k_put_descs(DevBlock *table, DescChunk c)
 {
     const uint32_t t = threadIdx.x;
     if (t < c.count) table[c.first + t] = c.d[t];
-}
-
-// ------------------------------------------------------------------------------------------
-// Hash-chain segments (the consensus section's clock: H_{i+1} = SHA-256(H_i)
-// over the 32 digest bytes).  One segment per lane: steps[i] single-block
-// hashes from start[i], compared with end[i].
-// ------------------------------------------------------------------------------------------
-__global__ void k_poh_zero(unsigned long long *count) { *count = 0; }
-
-__global__ void __launch_bounds__(kWG) ACE_WAVES(8) k_poh_verify(const uint8_t *__restrict__ start,
-                                                   const uint8_t *__restrict__ end,
-                                                   const uint32_t *__restrict__ steps,
-                                                   uint32_t uniform_steps, uint64_t n,
-                                                   uint32_t *__restrict__ bitmask,
-                                                   unsigned long long *__restrict__ count)
-{
-    const uint64_t i0 = 64ull * ((uint64_t)blockIdx.x * kWavesPerWG + (threadIdx.x >> 6));
-    if (i0 >= n) return;  // whole wave past the end
-    const uint64_t i = i0 + lane_id();
-    const bool live = i < n;
-    State h;
-    uint32_t T = 0;
-    if (live) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(start + 32ull * i);
-        const U4 a = load16(p), b = load16(p + 4);
-        h.h[0] = bswap32(a.x); h.h[1] = bswap32(a.y); h.h[2] = bswap32(a.z); h.h[3] = bswap32(a.w);
-        h.h[4] = bswap32(b.x); h.h[5] = bswap32(b.y); h.h[6] = bswap32(b.z); h.h[7] = bswap32(b.w);
-        T = steps ? steps[i] : uniform_steps;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) h.h[k] = 0;
-    }
-    for (uint32_t t = 0;; ++t) {
-        const bool run = live && t < T;
-        if (__ballot(run) == 0) break;
-        if (run) {
-            // the 32-byte value, 0x80, zeros, bit length 256: one block
-            uint32_t W[16];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) W[k] = h.h[k];
-            W[8] = 0x80000000u;
-#pragma unroll
-            for (int k = 9; k < 15; ++k) W[k] = 0u;
-            W[15] = 256u;
-            State s = initial_state();
-            compress_block(s, W);
-            h = s;
-        }
-    }
-    bool ok = false;
-    if (live) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(end + 32ull * i);
-        const U4 a = load16(p), b = load16(p + 4);
-        uint32_t d = 0;
-        d = or_xor(d, h.h[0], bswap32(a.x)); d = or_xor(d, h.h[1], bswap32(a.y));
-        d = or_xor(d, h.h[2], bswap32(a.z)); d = or_xor(d, h.h[3], bswap32(a.w));
-        d = or_xor(d, h.h[4], bswap32(b.x)); d = or_xor(d, h.h[5], bswap32(b.y));
-        d = or_xor(d, h.h[6], bswap32(b.z)); d = or_xor(d, h.h[7], bswap32(b.w));
-        ok = d == 0;
-    }
-    const unsigned long long m = __ballot(ok);
-    if (lane_id() == 0) {
-        bitmask[i0 >> 5] = (uint32_t)m;
-        if (i0 + 32 < n) bitmask[(i0 >> 5) + 1] = (uint32_t)(m >> 32);
-        const unsigned c = __popcll(m);
-        if (c) atomicAdd(count, (unsigned long long)c);
-    }
 }
 
 // Explicit instantiations used by the host entry points.

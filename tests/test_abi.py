@@ -214,6 +214,10 @@ def test_tuning_roundtrip_and_limits(lib):
             ace.set_tuning(verify_wgs_per_cu=0)
         with pytest.raises(ace.AceError):
             ace.set_tuning(aux_wgs_per_cu=65)
+        ace.set_tuning(derive_wgs_per_cu=0)          # 0: one workgroup per 256 identities
+        assert ace.get_tuning()["derive_wgs_per_cu"] == 0
+        with pytest.raises(ace.AceError):
+            ace.set_tuning(derive_wgs_per_cu=65)
     finally:
         ace.set_tuning(**old)
     assert ace.get_tuning() == old
