@@ -1,10 +1,12 @@
 // sha256_gfx950.h -- SHA-256 block computation as gfx950 (CDNA4) device code.
 //
 // One lane owns one hash chain.  The eight working variables and the
-// sixteen-word message-schedule window live in VGPRs; the loop is fully
-// unrolled so every round constant is a compile-time value that the
-// compiler materialises with s_mov_b32 into an SGPR and feeds to v_add3_u32
-// (gfx950 VOP3 takes no literal operands).  Per round: 3 v_alignbit_b32 +
+// sixteen-word message-schedule window live in VGPRs; round constants are
+// scalar operands (SGPRs) of v_add3_u32.  Two forms compute the same block:
+// `compress`, fully unrolled with compile-time constants, and
+// `compress_looped` (the kernels' default), whose rounds 16..63 run as a
+// three-iteration loop fed by one scalar load of sixteen constants per
+// iteration, which needs about half the VGPRs.  Per round: 3 v_alignbit_b32 +
 // 1 v_bitop3_b32 for each big sigma, 1 v_bitop3_b32 each for Ch and Maj,
 // 2 v_add3_u32 for T1, 1 v_add_u32 for e, 1 v_add3_u32 for a; per schedule
 // word 2 v_alignbit + 1 v_lshrrev + 1 v_bitop3 per small sigma and
@@ -168,42 +170,6 @@ __device__ __forceinline__ void compress_block(State &s, uint32_t (&W)[16])
 #else
     compress(s, W);
 #endif
-}
-
-// Compression of a block whose words 8..15 are the fixed tail of a 32-byte
-// message after a 64-byte key block: 0x80 marker, zeros, bit length
-// (64 + 32) * 8 = 768.  Used for HMAC outer hashes and for 32-byte inputs.
-__device__ __forceinline__ State compress_32(const State &in, const uint32_t (&m)[8])
-{
-    uint32_t W[16];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) W[i] = m[i];
-    W[8] = 0x80000000u;
-#pragma unroll
-    for (int i = 9; i < 15; ++i) W[i] = 0u;
-    W[15] = 768u;
-    State s = in;
-    compress(s, W);
-    return s;
-}
-
-// HMAC key midstates of a 32-byte key held as big-endian words k[0..7]:
-// F(IV, K0 ^ ipad) and F(IV, K0 ^ opad) with K0 = key || 0^32 (RFC 2104).
-__device__ __forceinline__ void key_midstates(const uint32_t (&k)[8], State &ipad, State &opad)
-{
-    uint32_t W[16];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) W[i] = k[i] ^ 0x36363636u;
-#pragma unroll
-    for (int i = 8; i < 16; ++i) W[i] = 0x36363636u;
-    ipad = initial_state();
-    compress(ipad, W);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) W[i] = k[i] ^ 0x5c5c5c5cu;
-#pragma unroll
-    for (int i = 8; i < 16; ++i) W[i] = 0x5c5c5c5cu;
-    opad = initial_state();
-    compress(opad, W);
 }
 
 }  // namespace ace
