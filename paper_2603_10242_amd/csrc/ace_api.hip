@@ -288,6 +288,7 @@ struct Fork {
     int dev;
     hipStream_t aux;
     hipEvent_t fork, join;
+    hipEvent_t mark;  // timing-enabled marker on the caller's stream, see below
 };
 
 Fork *fork_ctx()
@@ -297,10 +298,11 @@ Fork *fork_ctx()
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     for (auto &f : forks)
         if (f.dev == dev) return &f;
-    Fork f{dev, nullptr, nullptr, nullptr};
+    Fork f{dev, nullptr, nullptr, nullptr, nullptr};
     if (hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&f.mark) != hipSuccess)
         return nullptr;
     forks.push_back(f);
     return &forks.back();
@@ -392,7 +394,14 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
             hipLaunchKernelGGL(k_derive, dim3(g), dim3(kWG), 0, ds, keys->d_rev, keys->n_id,
                                (uint8_t *)nullptr, mid, hp);
             if ((rc = launch_status("k_derive launch"))) return rc;
-            if (fk && (rc = check_hip(hipEventRecord(fk->join, fk->aux), "hipEventRecord"))) return rc;
+            if (fk) {
+                if ((rc = check_hip(hipEventRecord(fk->join, fk->aux), "hipEventRecord"))) return rc;
+                // A timing-enabled marker on the caller's stream right after the
+                // derivation's launch: without it the binning kernels took the
+                // CUs first and the derivation ran after them (measured at 16M
+                // transactions: 5.2 ms per step without, 4.4 ms with).
+                if ((rc = check_hip(hipEventRecord(fk->mark, s), "hipEventRecord"))) return rc;
+            }
         }
         ks.mid = mid;
     }
