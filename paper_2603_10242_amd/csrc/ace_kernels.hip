@@ -130,15 +130,192 @@ struct TxRef {
 template <bool ATTEST>
 constexpr uint32_t check_stride() { return ATTEST ? 72u : 32u; }
 
+// The 17 dwords from dword 16 b of a message's aligned area: the 64 bytes of
+// message block b after the alignment shift, plus the next dword.  Either the
+// loads stay within kOverread bytes past the message end inside the block's
+// message area (overread_ok), or every address is clamped to a dword that
+// holds message bytes: nothing outside the caller's buffers is touched, and
+// bytes past the message end only feed words the padding overwrites.
+__device__ __forceinline__ void load_window(uint32_t (&D)[17], const uint32_t *q, int64_t rb,
+                                            bool overread_ok, const uint32_t *A0, uint64_t last,
+                                            uint32_t b)
+{
+    if (overread_ok || rb >= 68) {
+        // whole 16-byte loads and dword 16 (with 68 message bytes left every
+        // dword holds some)
+        const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
+        D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
+        D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
+        D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
+        D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
+        D[16] = load32(q + 16);
+    } else {
+        // the last message before the end of its block's area
+#pragma unroll
+        for (int k = 0; k < 17; ++k) {
+            const uint64_t idx = 16ull * b + k;
+            D[k] = load32(A0 + (idx < last ? idx : last));
+        }
+        // keeps these loads in this branch: merged with the other branch's
+        // they became 17 dword loads on the common path
+        __asm__ volatile("" ::: "memory");
+    }
+}
+
+// Where a lane's message blocks come from and how the last one is padded.
+struct LaneGeom {
+    uint32_t nb;         // message blocks (0 for a dead lane)
+    uint32_t sel;        // byte selector of the alignment shift, big-endian
+    const uint32_t *A0;  // dword-aligned start of the message area
+    uint64_t last;       // last dword index that holds message bytes
+    uint32_t len_hi, len_lo;  // bit length in the final block
+};
+
+template <bool ATTEST>
+__device__ __forceinline__ LaneGeom lane_geom(bool live, const TxRef &t)
+{
+    LaneGeom g;
+    const uint64_t L = t.L;
+    g.nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(t.msg);
+    const uint32_t sh = (uint32_t)addr & 3u;
+    g.sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
+    const uint64_t lim = (uint64_t)sh + L;   // dword k holds message bytes iff 4k < lim
+    g.last = lim ? ((lim - 1) >> 2) : 0;
+    // an empty message without overread room reads its dwords from the check
+    // record (bytes the padding overwrites)
+    g.A0 = (lim || t.overread_ok) ? reinterpret_cast<const uint32_t *>(addr - sh)
+                                  : reinterpret_cast<const uint32_t *>(t.tag);
+    // the HMAC inner hash counts the 64-byte key block before the message
+    const uint64_t bits = ((ATTEST ? 0 : 64) + L) << 3;
+    g.len_hi = (uint32_t)(bits >> 32);
+    g.len_lo = (uint32_t)bits;
+    return g;
+}
+
+// The message blocks of one lane, chained onto S: each block's window is
+// loaded when the block starts.
+__device__ __forceinline__ void message_blocks(State &S, bool live, bool overread_ok, const LaneGeom &g,
+                                               int64_t L)
+{
+    // a do-while with the wave's vote at the end: with the vote at the top the
+    // state was copied twice per block
+    const uint32_t *q = g.A0;  // dword 16 b of the message area, advanced per block
+    int64_t rb = L;            // message bytes from this block on
+    uint32_t b = 0;
+    bool run = live;           // a live lane has at least one block
+    if (__ballot(run)) do {
+        if (run) {
+            uint32_t W[16];
+            uint32_t D[17];
+            load_window(D, q, rb, overread_ok, g.A0, g.last, b);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], g.sel);
+            if (rb < 64) {
+                // padding: word jf holds byte rb (the 0x80 marker) after its c
+                // message bytes; earlier words are message, later ones zero
+                const int32_t r0 = (int32_t)rb;
+                const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
+                const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
+                const uint32_t keep = ~(0xFFFFFFFFu >> c8);
+                const uint32_t pad = 0x80000000u >> c8;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t part = (W[j] & keep) | pad;
+                    W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
+                }
+                if (b + 1 == g.nb) {
+                    W[14] = g.len_hi;
+                    W[15] = g.len_lo;
+                }
+            }
+            compress_block(S, W);
+        }
+        ++b; q += 16; rb -= 64;
+        run = live && b < g.nb;
+    } while (__ballot(run) != 0);
+}
+
+// Dwords of a transaction's check record: the credential (HMAC form), or
+// obj_hash (8) || domain (2) || credential (8) (paper form of Def. 3.1, with
+// the payload as the message).
+template <bool ATTEST>
+constexpr int check_words() { return ATTEST ? 18 : 8; }
+
+template <bool ATTEST>
+__device__ __forceinline__ void load_check(const uint8_t *tag, uint32_t (&C)[check_words<ATTEST>()])
+{
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(tag);
+    const U4 a = load16(p), c = load16(p + 4);
+    C[0] = a.x; C[1] = a.y; C[2] = a.z; C[3] = a.w;
+    C[4] = c.x; C[5] = c.y; C[6] = c.z; C[7] = c.w;
+    if constexpr (ATTEST) {
+        const U4 e = load16(p + 8), f = load16(p + 12);
+        C[8] = e.x; C[9] = e.y; C[10] = e.z; C[11] = e.w;
+        C[12] = f.x; C[13] = f.y; C[14] = f.z; C[15] = f.w;
+        C[16] = load32(p + 16); C[17] = load32(p + 17);
+    }
+}
+
+// After the message blocks: S is the HMAC inner state (HMAC form) or
+// SHA-256(P) (paper form).  Paper form: compare S with obj_hash, then the
+// HMAC inner block over obj_hash || domain (40 bytes, bit length
+// (64 + 40) * 8).  Both: the outer hash F(opad, inner digest || 0x80 || 0 ||
+// 768) and the constant-time compare with the credential.
+template <bool ATTEST>
+__device__ __forceinline__ bool lane_result(bool live, State S, const State &ipad, const State &opad,
+                                            const uint32_t (&C)[check_words<ATTEST>()])
+{
+    uint32_t d = 0;
+    if constexpr (ATTEST) {
+        uint32_t W[16];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) W[i] = bswap32(C[i]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d = or_xor(d, S.h[i], W[i]);
+        W[10] = 0x80000000u;
+#pragma unroll
+        for (int i = 11; i < 15; ++i) W[i] = 0u;
+        W[15] = (64u + 40u) * 8u;
+        State T = ipad;
+        compress_block(T, W);
+        S = T;
+    }
+    {
+        uint32_t W[16];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) W[i] = S.h[i];
+        W[8] = 0x80000000u;
+#pragma unroll
+        for (int i = 9; i < 15; ++i) W[i] = 0u;
+        W[15] = 768u;
+        State T = opad;
+        compress_block(T, W);
+        S = T;
+    }
+    constexpr int c0 = ATTEST ? 10 : 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) d = or_xor(d, S.h[i], bswap32(C[c0 + i]));
+    return live && d == 0;
+}
+
+__device__ __forceinline__ void load_midstates(const uint32_t *mid, uint32_t (&M)[16])
+{
+    // both halves of the 64-byte row at once: one cache line, fetched once
+    const U4 a = load16(mid), b = load16(mid + 4), c = load16(mid + 8), e = load16(mid + 12);
+    M[0] = a.x; M[1] = a.y; M[2] = a.z; M[3] = a.w; M[4] = b.x; M[5] = b.y; M[6] = b.z; M[7] = b.w;
+    M[8] = c.x; M[9] = c.y; M[10] = c.z; M[11] = c.w; M[12] = e.x; M[13] = e.y; M[14] = e.z; M[15] = e.w;
+}
+
 // HMAC form: valid iff HMAC(k, msg) == credential.
 // Paper form (ATTEST): the message is the payload P; valid iff SHA-256(P) ==
 // obj_hash (payload binding) and HMAC(k, obj_hash || domain) == credential.
 template <bool PER_TX_KEYS, bool ATTEST>
 __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const HkdfPrep *prep)
 {
-    State S, ipad, opad;
+    State ipad, opad;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { S.h[i] = 0; ipad.h[i] = 0; opad.h[i] = 0; }
+    for (int i = 0; i < 8; ++i) { ipad.h[i] = 0; opad.h[i] = 0; }
     if constexpr (PER_TX_KEYS) {
         uint32_t rv[8];
         if (live) {
@@ -154,146 +331,22 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
         derive_lane(live, rv, *prep, key, ipad, opad);
     } else {
         if (live) {
-            // both halves of the 64-byte row at once: one cache line, fetched once
-            const U4 a = load16(t.mid), b = load16(t.mid + 4);
-            const U4 c = load16(t.mid + 8), e = load16(t.mid + 12);
-            ipad.h[0] = a.x; ipad.h[1] = a.y; ipad.h[2] = a.z; ipad.h[3] = a.w;
-            ipad.h[4] = b.x; ipad.h[5] = b.y; ipad.h[6] = b.z; ipad.h[7] = b.w;
-            opad.h[0] = c.x; opad.h[1] = c.y; opad.h[2] = c.z; opad.h[3] = c.w;
-            opad.h[4] = e.x; opad.h[5] = e.y; opad.h[6] = e.z; opad.h[7] = e.w;
+            uint32_t M[16];
+            load_midstates(t.mid, M);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) { ipad.h[i] = M[i]; opad.h[i] = M[8 + i]; }
         }
     }
     // the message chain starts from the ipad state (HMAC inner hash) or, for
     // the payload digest, from the initial value
-    if constexpr (ATTEST) S = initial_state();
-    else S = ipad;
-
-    const uint64_t L = t.L;
-    const uint32_t nb = live ? (uint32_t)((L + 9 + 63) >> 6) : 0u;  // message blocks
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(t.msg);
-    const uint32_t sh = (uint32_t)addr & 3u;
-    const uint32_t sel = 0x00010203u + sh * 0x01010101u;  // bytes sh..sh+3 of {hi:lo}, big-endian
-    const uint64_t lim = (uint64_t)sh + L;                  // dword k holds message bytes iff 4k < lim
-    const uint64_t last = lim ? ((lim - 1) >> 2) : 0;
-    // Loads either stay within kOverread bytes past the message end inside the
-    // block's message area (overread_ok), or every address is clamped to a
-    // dword that holds message bytes (for an empty message, the check
-    // record): nothing outside the caller's buffers is touched, and bytes past
-    // the message end only feed words the padding overwrites.
-    const uint32_t *A0 = (lim || t.overread_ok) ? reinterpret_cast<const uint32_t *>(addr - sh)
-                                                : reinterpret_cast<const uint32_t *>(t.tag);
-    // bit length: the HMAC inner hash counts the 64-byte key block before the message
-    const uint64_t bits = ((ATTEST ? 0 : 64) + L) << 3;
-    const uint32_t len_hi = (uint32_t)(bits >> 32);
-    const uint32_t len_lo = (uint32_t)bits;
-
-    // Message blocks.  Only these vary in number between lanes (in the binned
-    // kernel not at all within a wave); the fixed-form blocks after the loop
-    // run once for every lane.
-    const uint32_t *q = A0;  // dword 16 b of the message area, advanced per block
-    int64_t rb = (int64_t)L;  // message bytes from this block on
-    for (uint32_t b = 0;; ++b, q += 16, rb -= 64) {
-        const bool run = live && b < nb;
-        if (__ballot(run) == 0) break;
-        if (run) {
-            uint32_t W[16];
-            uint32_t D[17];
-            if (t.overread_ok || rb >= 64) {
-                // whole 16-byte loads; past the message end they only read bytes of
-                // the same block's message area, which the padding overwrites
-                const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
-                D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
-                D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
-                D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
-                D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
-                const uint64_t k16 = 16ull * b + 16;
-                D[16] = load32(t.overread_ok ? q + 16 : A0 + (k16 < last ? k16 : last));
-            } else {
-                // the last message before the end of its block's area: every
-                // dword address is clamped to one that holds message bytes
+    State S = ATTEST ? initial_state() : ipad;
+    const LaneGeom g = lane_geom<ATTEST>(live, t);
+    message_blocks(S, live, t.overread_ok, g, (int64_t)t.L);
+    uint32_t C[check_words<ATTEST>()];
 #pragma unroll
-                for (int k = 0; k < 17; ++k) {
-                    const uint64_t idx = 16ull * b + k;
-                    D[k] = load32(A0 + (idx < last ? idx : last));
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
-            if (rb < 64) {
-                // padding: word jf holds byte rb (the 0x80 marker) after its c
-                // message bytes; earlier words are message, later ones zero
-                const int32_t r0 = (int32_t)rb;
-                const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
-                const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
-                const uint32_t keep = ~(0xFFFFFFFFu >> c8);
-                const uint32_t pad = 0x80000000u >> c8;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const uint32_t part = (W[j] & keep) | pad;
-                    W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
-                }
-                if (b + 1 == nb) {
-                    W[14] = len_hi;
-                    W[15] = len_lo;
-                }
-            }
-            compress_block(S, W);
-        }
-    }
-
-    uint32_t bind = 0;  // paper form: OR of SHA-256(P) ^ obj_hash
-    if constexpr (ATTEST) {
-        // S = SHA-256(P): compare with obj_hash, then the HMAC inner block over
-        // obj_hash || domain (40 bytes, bit length (64 + 40) * 8)
-        uint32_t W[16];
-#pragma unroll
-        for (int i = 0; i < 10; ++i) W[i] = 0;
-        if (live) {
-            const uint32_t *ap = reinterpret_cast<const uint32_t *>(t.tag);
-            const U4 a0 = load16(ap), a1 = load16(ap + 4);
-            const uint32_t d0 = ap[8], d1 = ap[9];
-            W[0] = bswap32(a0.x); W[1] = bswap32(a0.y); W[2] = bswap32(a0.z); W[3] = bswap32(a0.w);
-            W[4] = bswap32(a1.x); W[5] = bswap32(a1.y); W[6] = bswap32(a1.z); W[7] = bswap32(a1.w);
-            W[8] = bswap32(d0);
-            W[9] = bswap32(d1);
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bind = or_xor(bind, S.h[i], W[i]);
-        W[10] = 0x80000000u;
-#pragma unroll
-        for (int i = 11; i < 15; ++i) W[i] = 0u;
-        W[15] = (64u + 40u) * 8u;
-        State T = ipad;
-        compress_block(T, W);
-        S = T;
-    }
-
-    // outer hash: F(opad state, inner digest || 0x80 || 0 || 768)
-    {
-        uint32_t W[16];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) W[i] = S.h[i];
-        W[8] = 0x80000000u;
-#pragma unroll
-        for (int i = 9; i < 15; ++i) W[i] = 0u;
-        W[15] = 768u;
-        State T = opad;
-        compress_block(T, W);
-        S = T;
-    }
-
-    bool ok = false;
-    if (live) {
-        const uint32_t *tp = reinterpret_cast<const uint32_t *>(t.tag) + (ATTEST ? 10 : 0);
-        const U4 a = load16(tp), c = load16(tp + 4);
-        uint32_t d = bind;
-        d = or_xor(d, S.h[0], bswap32(a.x)); d = or_xor(d, S.h[1], bswap32(a.y));
-        d = or_xor(d, S.h[2], bswap32(a.z)); d = or_xor(d, S.h[3], bswap32(a.w));
-        d = or_xor(d, S.h[4], bswap32(c.x)); d = or_xor(d, S.h[5], bswap32(c.y));
-        d = or_xor(d, S.h[6], bswap32(c.z)); d = or_xor(d, S.h[7], bswap32(c.w));
-        ok = d == 0;
-    }
-    return ok;
+    for (int i = 0; i < check_words<ATTEST>(); ++i) C[i] = 0;
+    if (live) load_check<ATTEST>(t.tag, C);
+    return lane_result<ATTEST>(live, S, ipad, opad, C);
 }
 
 // Loads what one lane needs about transaction i of block d.  Returns whether
@@ -491,6 +544,26 @@ constexpr uint32_t kGrab = 8;
 // k_verify, binned form: wave tile w covers bin-order positions 64w..64w+63,
 // all in one bin; verdicts go to a bin-order bitmap.
 // ------------------------------------------------------------------------------------------
+// A transaction from its bin-order entry: e = block << 40 | index, r its
+// record.  Returns whether it can be valid at all.
+template <bool ATTEST>
+__device__ __forceinline__ bool binned_tx(const Batch &bt, const Totals &T, const KeySource &ks,
+                                          unsigned long long e, const TxRec &r, TxRef &t)
+{
+    const uint32_t b = (uint32_t)(e >> 40);
+    const uint64_t i = e & ((1ull << 40) - 1);
+    if (r.len == kRecWide) return load_tx<ATTEST>(get_block(bt, T, b), i, ks, t);  // 2 GiB or more
+    const bool live = r.id != kRecInvalid;
+    const uint32_t who = live ? r.id : 0u;
+    t.msg = reinterpret_cast<const uint8_t *>(r.addr);
+    t.L = r.len & ~kRecNearEnd;
+    t.overread_ok = (r.len & kRecNearEnd) == 0;
+    t.mid = ks.mid ? ks.mid + 16ull * who : nullptr;
+    t.rev = ks.rev ? ks.rev + 32ull * who : nullptr;
+    t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) + (uint64_t)check_stride<ATTEST>() * i;
+    return live;
+}
+
 template <bool PER_TX_KEYS, bool PERSISTENT, bool ATTEST>
 __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PERSISTENT ? 6 : 7) : 8)) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
@@ -545,25 +618,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
         const bool active = k - ostart[o] < ocount[o];
         TxRef t{};
         bool live = false;
-        if (active) {
-            const unsigned long long e = perm[k];
-            const TxRec r = rec[k];
-            const uint32_t b = (uint32_t)(e >> 40);
-            const uint64_t i = e & ((1ull << 40) - 1);
-            if (r.len == kRecWide) {
-                live = load_tx<ATTEST>(get_block(bt, T, b), i, ks, t);  // message of 2 GiB or more
-            } else {
-                live = r.id != kRecInvalid;
-                const uint32_t who = live ? r.id : 0u;
-                t.msg = reinterpret_cast<const uint8_t *>(r.addr);
-                t.L = r.len & ~kRecNearEnd;
-                t.overread_ok = (r.len & kRecNearEnd) == 0;
-                t.mid = ks.mid ? ks.mid + 16ull * who : nullptr;
-                t.rev = ks.rev ? ks.rev + 32ull * who : nullptr;
-                t.tag = (T.inline_one ? bt.one.tag : bt.table[b].tag) +
-                        (uint64_t)check_stride<ATTEST>() * i;
-            }
-        }
+        if (active) live = binned_tx<ATTEST>(bt, T, ks, perm[k], rec[k], t);
         const bool valid = verify_lane<PER_TX_KEYS, ATTEST>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
         if (lane == 0) {
