@@ -262,7 +262,16 @@ __device__ __forceinline__ void load_check(const uint8_t *tag, uint32_t (&C)[che
 // HMAC inner block over obj_hash || domain (40 bytes, bit length
 // (64 + 40) * 8).  Both: the outer hash F(opad, inner digest || 0x80 || 0 ||
 // 768) and the constant-time compare with the credential.
-template <bool ATTEST>
+// FOLD: the fixed-form blocks use compress_fold (50 fewer VALU per block, a
+// few more registers; kernels at their register limit keep the plain form).
+template <bool FOLD>
+__device__ __forceinline__ void compress_tail_block(State &s, uint32_t (&W)[16])
+{
+    if constexpr (FOLD) compress_fold(s, W);
+    else compress_block(s, W);
+}
+
+template <bool ATTEST, bool FOLD>
 __device__ __forceinline__ bool lane_result(bool live, State S, const State &ipad, const State &opad,
                                             const uint32_t (&C)[check_words<ATTEST>()])
 {
@@ -278,7 +287,7 @@ __device__ __forceinline__ bool lane_result(bool live, State S, const State &ipa
         for (int i = 11; i < 15; ++i) W[i] = 0u;
         W[15] = (64u + 40u) * 8u;
         State T = ipad;
-        compress_block(T, W);
+        compress_tail_block<FOLD>(T, W);
         S = T;
     }
     {
@@ -290,7 +299,7 @@ __device__ __forceinline__ bool lane_result(bool live, State S, const State &ipa
         for (int i = 9; i < 15; ++i) W[i] = 0u;
         W[15] = 768u;
         State T = opad;
-        compress_block(T, W);
+        compress_tail_block<FOLD>(T, W);
         S = T;
     }
     constexpr int c0 = ATTEST ? 10 : 0;
@@ -310,7 +319,7 @@ __device__ __forceinline__ void load_midstates(const uint32_t *mid, uint32_t (&M
 // HMAC form: valid iff HMAC(k, msg) == credential.
 // Paper form (ATTEST): the message is the payload P; valid iff SHA-256(P) ==
 // obj_hash (payload binding) and HMAC(k, obj_hash || domain) == credential.
-template <bool PER_TX_KEYS, bool ATTEST>
+template <bool PER_TX_KEYS, bool ATTEST, bool FOLD>
 __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const HkdfPrep *prep)
 {
     State ipad, opad;
@@ -346,7 +355,7 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
 #pragma unroll
     for (int i = 0; i < check_words<ATTEST>(); ++i) C[i] = 0;
     if (live) load_check<ATTEST>(t.tag, C);
-    return lane_result<ATTEST>(live, S, ipad, opad, C);
+    return lane_result<ATTEST, FOLD>(live, S, ipad, opad, C);
 }
 
 // Loads what one lane needs about transaction i of block d.  Returns whether
@@ -391,7 +400,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? 6 :
         TxRef t{};
         bool live = false;
         if (active) live = load_tx<ATTEST>(d, i, ks, t);
-        const bool valid = verify_lane<PER_TX_KEYS, ATTEST>(live, t, &prep) && live;
+        const bool valid = verify_lane<PER_TX_KEYS, ATTEST, !ATTEST>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
         if (lane_id() == 0) {
             d.bitmask[i0 >> 5] = (uint32_t)m;
@@ -619,7 +628,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
         TxRef t{};
         bool live = false;
         if (active) live = binned_tx<ATTEST>(bt, T, ks, perm[k], rec[k], t);
-        const bool valid = verify_lane<PER_TX_KEYS, ATTEST>(live, t, &prep) && live;
+        const bool valid = verify_lane<PER_TX_KEYS, ATTEST, !PERSISTENT>(live, t, &prep) && live;
         const unsigned long long m = __ballot(valid);
         if (lane == 0) {
             vperm[2 * w] = (uint32_t)m;

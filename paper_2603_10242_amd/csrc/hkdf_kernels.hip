@@ -120,7 +120,7 @@ __device__ __forceinline__ void compress_tail32(State &in, const State &m)
 #pragma unroll
     for (int i = 9; i < 15; ++i) W[i] = 0u;
     W[15] = 768u;
-    compress_block(in, W);
+    compress_fold(in, W);
 }
 
 // HKDF-SHA256 (RFC 5869, L = 32) of one 32-byte root entropy rv (big-endian

@@ -158,6 +158,39 @@ __device__ __forceinline__ void compress_looped(State &s, uint32_t (&W)[16])
     s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
 }
 
+// The looped form with rounds 16..31 unrolled as well, for blocks whose
+// words 8..15 are constants at the call site (an HMAC block over a 32-byte
+// digest, a key block's pad bytes): those words then fold into the first
+// sixteen schedule words instead of being computed on (zero words drop out
+// of the sums, sigma0 of a constant is a constant).
+__device__ __forceinline__ void compress_fold(State &s, uint32_t (&W)[16])
+{
+    uint32_t a = s.h[0], b = s.h[1], c = s.h[2], d = s.h[3];
+    uint32_t e = s.h[4], f = s.h[5], g = s.h[6], h = s.h[7];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) round_step(a, b, c, d, e, f, g, h, W[j], kRound[j]);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t wt = small_sigma1(W[(j - 2) & 15]) + W[(j - 7) & 15] +
+                            small_sigma0(W[(j - 15) & 15]) + W[j];
+        W[j] = wt;
+        round_step(a, b, c, d, e, f, g, h, wt, kRound[16 + j]);
+    }
+#pragma nounroll
+    for (int q = 2; q < 4; ++q) {
+        const RoundConsts16 kq = *reinterpret_cast<const RoundConsts16 *>(&kRoundTable[16 * q]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t wt = small_sigma1(W[(j - 2) & 15]) + W[(j - 7) & 15] +
+                                small_sigma0(W[(j - 15) & 15]) + W[j];
+            W[j] = wt;
+            round_step(a, b, c, d, e, f, g, h, wt, kq.k[j]);
+        }
+    }
+    s.h[0] += a; s.h[1] += b; s.h[2] += c; s.h[3] += d;
+    s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
+}
+
 #ifndef ACE_COMPRESS_LOOPED
 #define ACE_COMPRESS_LOOPED 1
 #endif
