@@ -91,23 +91,27 @@ __device__ void hkdf_prepare(const Params &hp, HkdfPrep &out)
     }
 }
 
-// HMAC midstates F(IV, K0 ^ ipad) and F(IV, K0 ^ opad) of a 32-byte key held
-// as state words (K0 = key || 0^32): one call site, two passes.
+// HMAC midstate F(IV, K0 ^ pad) of a 32-byte key held as state words
+// (K0 = key || 0^32): words 8..15 of the block are the pad pattern itself.
+template <uint32_t PAD>
+__device__ __forceinline__ State hmac_midstate(const State &k)
+{
+    uint32_t W[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) W[i] = k.h[i] ^ PAD;
+#pragma unroll
+    for (int i = 8; i < 16; ++i) W[i] = PAD;
+    State t = initial_state();
+    compress_fold(t, W);
+    return t;
+}
+
+// Both midstates; each pass has its pad as a constant, so its words 8..15
+// fold into the schedule.
 __device__ __forceinline__ void hmac_midstates(const State &k, State &ipad, State &opad)
 {
-#pragma nounroll
-    for (int pass = 0; pass < 2; ++pass) {
-        const uint32_t pad = pass ? 0x5c5c5c5cu : 0x36363636u;
-        uint32_t W[16];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) W[i] = k.h[i] ^ pad;
-#pragma unroll
-        for (int i = 8; i < 16; ++i) W[i] = pad;
-        State t = initial_state();
-        compress_block(t, W);
-        if (pass) opad = t;
-        else ipad = t;
-    }
+    ipad = hmac_midstate<0x36363636u>(k);
+    opad = hmac_midstate<0x5c5c5c5cu>(k);
 }
 
 // F(in, m || 0x80 || 0 || 768): a 32-byte message after a 64-byte key block.
