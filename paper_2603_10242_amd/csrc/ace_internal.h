@@ -79,7 +79,7 @@ struct HkdfParams {
 
 // Several HKDF parameter sets in one launch (one per grid row): short salts
 // and infos only, so that the set fits the kernel's argument block.
-constexpr uint32_t kMultiStreams = 8;
+constexpr uint32_t kMultiStreams = 16;
 constexpr uint32_t kMultiSalt = 64;
 constexpr uint32_t kMultiInfo = 64;
 struct StreamParams {

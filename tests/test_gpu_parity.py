@@ -109,7 +109,7 @@ def _info_strings():
 @pytest.mark.parametrize("n_id", [1, 300, 4097])
 def test_derive_keys_multi(ace, n_id):
     """Keys and midstates of the paper's purpose streams, the validator streams
-    and eleven slot domains (19 streams: three launches of up to 8)."""
+    and eleven slot domains (19 streams: two launches of up to 16)."""
     import torch
     note("derive multi n_id=%d" % n_id)
     r = np.random.Generator(np.random.PCG64(4242 + n_id))
