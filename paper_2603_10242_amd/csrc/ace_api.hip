@@ -282,8 +282,10 @@ DevBlock dev_block(const ace_block &k)
 
 // A second stream per thread and device on which the key derivation runs
 // beside the binning passes: forked from and joined back to the caller's
-// stream with events (under graph capture, two branches of the graph).  The
-// streams and events live until the process ends.
+// stream with events (under graph capture, two branches of the graph).  When
+// a thread ends, its contexts go to a process-wide free list that later
+// threads take from, so threads that come and go do not add streams; the
+// list itself is never destroyed (no HIP calls during process exit).
 struct Fork {
     int dev;
     hipStream_t aux;
@@ -291,21 +293,58 @@ struct Fork {
     hipEvent_t mark;  // timing-enabled marker on the caller's stream, see below
 };
 
+std::mutex g_fork_mu;
+std::vector<Fork> *g_fork_free = new std::vector<Fork>();
+
+struct ForkCache {
+    std::vector<Fork> forks;
+    ~ForkCache()
+    {
+        std::lock_guard<std::mutex> lock(g_fork_mu);
+        for (const Fork &f : forks) g_fork_free->push_back(f);
+    }
+};
+
+bool fork_create(int dev, Fork &f)
+{
+    f = Fork{dev, nullptr, nullptr, nullptr, nullptr};
+    bool ok = hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&f.join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreate(&f.mark) == hipSuccess;
+    if (!ok) {
+        if (f.mark) (void)hipEventDestroy(f.mark);
+        if (f.join) (void)hipEventDestroy(f.join);
+        if (f.fork) (void)hipEventDestroy(f.fork);
+        if (f.aux) (void)hipStreamDestroy(f.aux);
+    }
+    return ok;
+}
+
 Fork *fork_ctx()
 {
-    thread_local std::vector<Fork> forks;
+    thread_local ForkCache cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    for (auto &f : forks)
+    for (auto &f : cache.forks)
         if (f.dev == dev) return &f;
-    Fork f{dev, nullptr, nullptr, nullptr, nullptr};
-    if (hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreate(&f.mark) != hipSuccess)
-        return nullptr;
-    forks.push_back(f);
-    return &forks.back();
+    Fork f{};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lock(g_fork_mu);
+        for (size_t i = 0; i < g_fork_free->size(); ++i) {
+            if ((*g_fork_free)[i].dev == dev) {
+                f = (*g_fork_free)[i];
+                (*g_fork_free)[i] = g_fork_free->back();
+                g_fork_free->pop_back();
+                have = true;
+                break;
+            }
+        }
+    }
+    if (!have && !fork_create(dev, f)) return nullptr;
+    cache.forks.push_back(f);
+    return &cache.forks.back();
 }
 
 // Workgroups of the count pass: each adds to a block's count at most once.

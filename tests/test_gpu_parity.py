@@ -130,6 +130,41 @@ def test_derive_keys_multi(ace, n_id):
         assert np.array_equal(got_mid[s], oracle.hmac_midstates(want[s]))
 
 
+def test_keys_in_call_from_short_lived_threads(ace):
+    """Keys derived in the call (the derivation on a second stream per thread)
+    from three rounds of eight threads that each verify one block and end:
+    later threads reuse the second-stream contexts of ended ones."""
+    import threading
+    import torch
+    note("keys in call from 24 short-lived threads")
+    w = W.config2()
+    rev = ace.to_device(w.rev)
+    ks = ace.rev_keyset(rev, w.salt, w.info)
+    step = w.n // 8
+    parts = [W.subset(w, i * step, (i + 1) * step) for i in range(8)]
+    errors = []
+
+    def one(part):
+        try:
+            torch.cuda.set_device(0)
+            blk = ace.upload_block(part.msg, part.off, part.ids, part.tags)
+            ace.verify_batch(ks, [blk], flags=MODES["binned"])
+            torch.cuda.synchronize()
+            mask, count = blk.result()
+            if count != int(part.truth.sum()) or not np.array_equal(mask, part.truth_bitmask()):
+                errors.append(part.name)
+        except Exception as e:  # reported below, in the test's thread
+            errors.append("%s: %r" % (part.name, e))
+
+    for _ in range(3):
+        threads = [threading.Thread(target=one, args=(p,)) for p in parts]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+    assert not errors, errors
+
+
 # ------------------------------------------------------------------ the tiny and block workloads
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("keys", ["midstate", "rev", "rev-per-tx"])
