@@ -672,7 +672,7 @@ def main() -> int:
     ap.add_argument("--arena-gib", type=int, default=8, help="serving: device arena")
     ap.add_argument("--staging-mib", type=int, default=2048, help="serving: pinned staging")
     ap.add_argument("--inflight", type=int, default=4, help="serving: batches in flight")
-    ap.add_argument("--sat-requests", type=int, default=4000)
+    ap.add_argument("--sat-requests", type=int, default=20000)
     ap.add_argument("--max-requests", type=int, default=20000)
     ap.add_argument("--point-seconds", type=float, default=1.5)
     ap.add_argument("--loads", type=float, nargs="+",

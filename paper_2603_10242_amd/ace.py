@@ -141,11 +141,25 @@ def _stream(stream) -> Optional[int]:
     return int(stream)
 
 
-def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+def _ptr(t: Optional[torch.Tensor], nbytes: int = 0, what: str = "tensor") -> Optional[int]:
+    """Device pointer of t (None passes through), after checking that it is a
+    contiguous device tensor of at least nbytes bytes: the library cannot see
+    the size of a device buffer, so an undersized one must not reach it."""
     if t is None:
         return None
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s: a contiguous device tensor is required" % what)
+    _require_bytes(t.numel() * t.element_size(), nbytes, what)
     return t.data_ptr()
+
+
+def _require_bytes(have: int, need: int, what: str) -> None:
+    if have < need:
+        raise ValueError("%s: %d bytes, %d needed" % (what, have, need))
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
 
 
 # ------------------------------------------------------------------------------ containers
@@ -160,10 +174,12 @@ class DeviceBlock:
     count: torch.Tensor     # int64 [1]
     n: int
 
-    def struct(self) -> ace_block:
-        return ace_block(_ptr(self.msg), _ptr(self.off),
-                         _ptr(self.ids), _ptr(self.tags), self.n, _ptr(self.bitmask),
-                         _ptr(self.count))
+    def struct(self, record_bytes: int = 32) -> ace_block:
+        n = self.n
+        return ace_block(_ptr(self.msg, 0, "msg"), _ptr(self.off, 8 * (n + 1), "off"),
+                         _ptr(self.ids, 4 * n, "ids"), _ptr(self.tags, record_bytes * n, "tags"), n,
+                         _ptr(self.bitmask, 4 * ((n + 31) // 32), "bitmask"),
+                         _ptr(self.count, 8, "count"))
 
     def result(self) -> tuple[np.ndarray, int]:
         m = self.bitmask.cpu().numpy().view(np.uint32).copy()
@@ -182,7 +198,8 @@ class DeviceKeyset:
     def struct(self) -> tuple[ace_keyset, list]:
         keep = [ctypes.create_string_buffer(self.salt, max(1, len(self.salt))),
                 ctypes.create_string_buffer(self.info, max(1, len(self.info)))]
-        ks = ace_keyset(self.kind, _ptr(self.mid), _ptr(self.rev), self.n_id,
+        ks = ace_keyset(self.kind, _ptr(self.mid, 64 * self.n_id, "midstates"),
+                        _ptr(self.rev, 32 * self.n_id, "rev"), self.n_id,
                         ctypes.addressof(keep[0]), len(self.salt), ctypes.addressof(keep[1]),
                         len(self.info))
         return ks, keep
@@ -206,13 +223,18 @@ def upload_block(msg, off, ids, tags, device="cuda", msg_dev: Optional[torch.Ten
     or (record_bytes=72) the attestation obj_hash || domain || credential.
     """
     n = int(np.asarray(ids).shape[0])
+    off = np.asarray(off, np.uint64)
+    if off.shape[0] != n + 1:
+        raise ValueError("off: %d entries for %d transactions" % (off.shape[0], n))
     if msg_dev is not None:
         m = msg_dev
+        if n and _nbytes(m) < int(off[-1]):
+            raise ValueError("msg_dev: %d bytes, offsets reach %d" % (_nbytes(m), int(off[-1])))
     else:
         host = np.asarray(msg, np.uint8).reshape(-1)
         # an all-empty batch still gets a real (4-byte) buffer to point at
         m = to_device(host if host.size else np.zeros(4, np.uint8), device=device)
-    return DeviceBlock(m, to_device(np.asarray(off, np.uint64), device=device),
+    return DeviceBlock(m, to_device(off, device=device),
                        to_device(np.asarray(ids, np.uint32), device=device),
                        to_device(np.asarray(tags, np.uint8).reshape(-1, record_bytes),
                                  device=device),
@@ -227,9 +249,10 @@ def derive_keys(rev: torch.Tensor, salt: bytes, info: bytes, key_out: Optional[t
     n_id = int(rev.shape[0]) if rev is not None else 0
     sb = ctypes.create_string_buffer(salt, max(1, len(salt)))
     ib = ctypes.create_string_buffer(info, max(1, len(info)))
-    _check(load().ace_derive_keys(_ptr(rev) if n_id else None, n_id, ctypes.addressof(sb),
-                                  len(salt), ctypes.addressof(ib), len(info), _ptr(key_out),
-                                  _ptr(mid_out), _stream(stream)))
+    _check(load().ace_derive_keys(_ptr(rev, 32 * n_id, "rev") if n_id else None, n_id,
+                                  ctypes.addressof(sb), len(salt), ctypes.addressof(ib), len(info),
+                                  _ptr(key_out, 32 * n_id, "key_out"),
+                                  _ptr(mid_out, 64 * n_id, "mid_out"), _stream(stream)))
 
 
 def derive_keys_multi(rev: torch.Tensor, streams: Sequence[tuple[bytes, bytes]],
@@ -245,14 +268,16 @@ def derive_keys_multi(rev: torch.Tensor, streams: Sequence[tuple[bytes, bytes]],
         ib = ctypes.create_string_buffer(info, max(1, len(info)))
         keep += [sb, ib]
         arr[k] = ace_hkdf_stream(ctypes.addressof(sb), len(salt), ctypes.addressof(ib), len(info))
-    _check(load().ace_derive_keys_multi(_ptr(rev) if n_id else None, n_id, arr, len(streams),
-                                        _ptr(key_out), _ptr(mid_out), _stream(stream)))
+    S = len(streams)
+    _check(load().ace_derive_keys_multi(_ptr(rev, 32 * n_id, "rev") if n_id else None, n_id, arr, S,
+                                        _ptr(key_out, 32 * n_id * S, "key_out"),
+                                        _ptr(mid_out, 64 * n_id * S, "mid_out"), _stream(stream)))
 
 
-def _blocks_array(blocks: Sequence[DeviceBlock]):
+def _blocks_array(blocks: Sequence[DeviceBlock], record_bytes: int = 32):
     arr = (ace_block * max(1, len(blocks)))()
     for i, b in enumerate(blocks):
-        arr[i] = b.struct()
+        arr[i] = b.struct(record_bytes)
     return arr
 
 
@@ -267,16 +292,17 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 
 def _verify(fn, keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
-            ws: Optional[torch.Tensor], flags: int, stream) -> torch.Tensor:
+            ws: Optional[torch.Tensor], flags: int, stream, record_bytes: int = 32) -> torch.Tensor:
     ks, keep = keyset.struct()
-    arr = _blocks_array(blocks)
+    arr = _blocks_array(blocks, record_bytes)
     lib = load()
     need = int(lib.ace_verify_workspace_size(ctypes.byref(ks), arr, len(blocks), flags))
     if need == 0 and len(blocks):
         _check(fn(ctypes.byref(ks), arr, len(blocks), None, 0, flags, None))
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = workspace(need, device=blocks[0].bitmask.device if blocks else "cuda")
-    _check(fn(ctypes.byref(ks), arr, len(blocks), _ptr(ws), ws.numel(), flags, _stream(stream)))
+    _check(fn(ctypes.byref(ks), arr, len(blocks), _ptr(ws, need, "workspace"), _nbytes(ws), flags,
+              _stream(stream)))
     return ws
 
 
@@ -290,7 +316,7 @@ def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
                         ws: Optional[torch.Tensor] = None, flags: int = 0,
                         stream=None) -> torch.Tensor:
     """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
-    return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream)
+    return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream, 72)
 
 
 def merkle_roots(trees: Sequence[tuple[torch.Tensor, torch.Tensor, int, torch.Tensor]],
@@ -299,15 +325,18 @@ def merkle_roots(trees: Sequence[tuple[torch.Tensor, torch.Tensor, int, torch.Te
     returns the workspace used."""
     arr = (ace_merkle_tree * max(1, len(trees)))()
     for i, (data, off, n, root) in enumerate(trees):
-        arr[i] = ace_merkle_tree(_ptr(data) if n else None, _ptr(off) if n else None, int(n),
-                                 _ptr(root))
+        n = int(n)
+        arr[i] = ace_merkle_tree(_ptr(data, 0, "data") if n else None,
+                                 _ptr(off, 8 * (n + 1), "off") if n else None, n,
+                                 _ptr(root, 32, "root"))
     lib = load()
     need = int(lib.ace_merkle_workspace_size(arr, len(trees)))
     if need == 0 and len(trees):
         _check(lib.ace_merkle_roots(arr, len(trees), None, 0, None))
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = workspace(need)
-    _check(lib.ace_merkle_roots(arr, len(trees), _ptr(ws), ws.numel(), _stream(stream)))
+    _check(lib.ace_merkle_roots(arr, len(trees), _ptr(ws, need, "workspace"), _nbytes(ws),
+                                _stream(stream)))
     return ws
 
 
@@ -316,11 +345,12 @@ def poh_verify(start: torch.Tensor, end: torch.Tensor, steps, bitmask: torch.Ten
     """ace_poh_verify: `steps` is an int (every segment) or a uint32 tensor [n]."""
     n = int(start.shape[0])
     if isinstance(steps, torch.Tensor):
-        d_steps, uni = _ptr(steps), 0
+        d_steps, uni = _ptr(steps, 4 * n, "steps"), 0
     else:
         d_steps, uni = None, int(steps)
-    _check(load().ace_poh_verify(_ptr(start), _ptr(end), d_steps, uni, n, _ptr(bitmask),
-                                 _ptr(count), _stream(stream)))
+    _check(load().ace_poh_verify(_ptr(start, 32 * n, "start"), _ptr(end, 32 * n, "end"), d_steps, uni,
+                                 n, _ptr(bitmask, 4 * ((n + 31) // 32), "bitmask"),
+                                 _ptr(count, 8, "count"), _stream(stream)))
 
 
 def valu_rate(iters: int = 20000, wgs_per_cu: int = 8, stream=None) -> float:
@@ -386,8 +416,9 @@ class Graph:
             raise AceError(ACE_ERR_INVALID_ARG, "bad graph arguments")
         self.ws = workspace(need, device=device)
         h = ctypes.c_void_p()
-        _check(lib.ace_graph_create(ctypes.byref(self._ks), max_blocks, max_tx, _ptr(self.ws),
-                                    self.ws.numel(), flags, ctypes.byref(h)))
+        _check(lib.ace_graph_create(ctypes.byref(self._ks), max_blocks, max_tx,
+                                    _ptr(self.ws, need, "workspace"), _nbytes(self.ws), flags,
+                                    ctypes.byref(h)))
         self._h = h
 
     def launch(self, blocks: Sequence[DeviceBlock], stream=None) -> None:
@@ -465,7 +496,8 @@ class Stream:
         _stream_protos(lib)
         ks, keep = keyset.struct()
         h = ctypes.c_void_p()
-        _check(lib.ace_stream_create(ctypes.byref(ks), _ptr(arena), arena.numel(), staging_bytes,
+        _check(lib.ace_stream_create(ctypes.byref(ks), _ptr(arena, 0, "arena"), _nbytes(arena),
+                                     staging_bytes,
                                      max_inflight, ACE_STREAM_PLAIN if plain else 0, ctypes.byref(h)))
         return cls(h, [keep, arena, keyset])
 

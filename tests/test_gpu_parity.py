@@ -165,6 +165,26 @@ def test_keys_in_call_from_short_lived_threads(ace):
     assert not errors, errors
 
 
+def test_binding_refuses_undersized_device_buffers(ace):
+    """Outputs smaller than the call would write are refused before any launch."""
+    import torch
+    rev = torch.zeros((100, 32), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError, match="mid_out"):
+        ace.derive_keys(rev, b"s", b"i", mid_out=torch.zeros((99, 16), dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError, match="key_out"):
+        ace.derive_keys_multi(rev, [(b"s", b"i"), (b"t", b"j")],
+                              key_out=torch.zeros((1, 100, 32), dtype=torch.uint8, device="cuda"))
+    w = W.config1()
+    blk = ace.upload_block(w.msg, w.off, w.ids, w.tags)
+    blk.bitmask = blk.bitmask[:-1].contiguous()
+    with pytest.raises(ValueError, match="bitmask"):
+        ace.verify_batch(ace.rev_keyset(ace.to_device(w.rev), w.salt, w.info), [blk])
+    s = torch.zeros((64, 32), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError, match="end"):
+        ace.poh_verify(s, s[:63].contiguous(), 3, torch.zeros(2, dtype=torch.int32, device="cuda"),
+                       torch.zeros(1, dtype=torch.int64, device="cuda"))
+
+
 # ------------------------------------------------------------------ the tiny and block workloads
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("keys", ["midstate", "rev", "rev-per-tx"])
