@@ -80,7 +80,8 @@ def _time(fn, reps: int = 5) -> float:
 
 
 def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20,
-        write: bool = True, log=print, out_dir: str | None = None) -> dict:
+        write: bool = True, log=print, out_dir: str | None = None,
+        derive_n: int = 16 << 20) -> dict:
     import torch
 
     from . import ace
@@ -149,14 +150,19 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
             best_aux = (t, apc)
 
     # 4. key derivation beside the binning passes (keys derived in the call):
-    # workgroups per CU, 0 = one workgroup per 256 identities
+    # workgroups per CU, 0 = one workgroup per 256 identities.  Measured on the
+    # throughput sweep's batch (16M transactions, 1M identities): the best
+    # share depends on how long the binning passes run beside the derivation,
+    # and at 4M transactions they end well before it.
     ace.set_tuning(aux_wgs_per_cu=int(best_aux[1]))
-    rks = ace.rev_keyset(ace.to_device(w.rev), w.salt, w.info)
+    wd = W.config3(n=derive_n, n_id=1 << 20)
+    dblk = ace.upload_block(wd.msg, wd.off, wd.ids, wd.tags)
+    rks = ace.rev_keyset(ace.to_device(wd.rev), wd.salt, wd.info)
     best_der = (float("inf"), default.get("derive_wgs_per_cu", 1))
     for dpc in (0, 1, 2, 4):
         ace.set_tuning(derive_wgs_per_cu=dpc)
-        t = _time(lambda: ace.verify_batch(rks, [blk], flags=ace.ACE_BUCKETED))
-        meas.append({"n": big, "n_id": int(w.n_id), "derive_wgs_per_cu": dpc, "ms": t})
+        t = _time(lambda: ace.verify_batch(rks, [dblk], flags=ace.ACE_BUCKETED))
+        meas.append({"n": derive_n, "n_id": int(wd.n_id), "derive_wgs_per_cu": dpc, "ms": t})
         log("derive %2d WG/CU beside binning: %.3f ms" % (dpc, t))
         if t < best_der[0]:
             best_der = (t, dpc)
