@@ -94,7 +94,8 @@ def sha256_iv() -> np.ndarray:
 
 def sha256_compress(state, block: bytes) -> np.ndarray:
     """One FIPS 180-4 block computation F(state, block); returns the new state."""
-    assert len(block) == 64
+    if len(block) != 64:
+        raise ValueError("a compression takes one 64-byte block")
     h = np.array(state, dtype=np.uint32).copy()
     _load().oracle_sha256_compress(_ptr(h, _u32p), _buf(block))
     return h
@@ -155,7 +156,8 @@ def verify_batch(keys: np.ndarray, msg: np.ndarray, off: np.ndarray, ids: np.nda
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     tags = np.ascontiguousarray(tags, dtype=np.uint8).reshape(-1, 32)
     n = ids.shape[0]
-    assert off.shape[0] == n + 1 and tags.shape[0] == n
+    if off.shape[0] != n + 1 or tags.shape[0] != n:
+        raise ValueError("off must hold n + 1 entries and tags n rows")
     mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
     cnt = ctypes.c_uint64(0)
     msg_arg = msg if msg.size else np.zeros(1, np.uint8)
@@ -182,7 +184,8 @@ def verify_attest(keys: np.ndarray, payload: np.ndarray, poff: np.ndarray, ids: 
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     att = np.ascontiguousarray(att, dtype=np.uint8).reshape(-1, 72)
     n = ids.shape[0]
-    assert poff.shape[0] == n + 1 and att.shape[0] == n
+    if poff.shape[0] != n + 1 or att.shape[0] != n:
+        raise ValueError("poff must hold n + 1 entries and att n rows")
     mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
     cnt = ctypes.c_uint64(0)
     p_arg = payload if payload.size else np.zeros(1, np.uint8)
@@ -200,7 +203,8 @@ def poh_verify(start: np.ndarray, end: np.ndarray, steps: np.ndarray,
     end = np.ascontiguousarray(end, dtype=np.uint8).reshape(-1, 32)
     steps = np.ascontiguousarray(steps, dtype=np.uint32)
     n = steps.shape[0]
-    assert start.shape[0] == n and end.shape[0] == n
+    if start.shape[0] != n or end.shape[0] != n:
+        raise ValueError("start and end must hold one row per segment")
     mask = np.zeros(max(1, (n + 31) // 32), np.uint32)
     cnt = ctypes.c_uint64(0)
     if n:
@@ -215,7 +219,8 @@ def merkle_roots(data: np.ndarray, off: np.ndarray, tree_sizes) -> np.ndarray:
     data = np.ascontiguousarray(data, dtype=np.uint8)
     off = np.ascontiguousarray(off, dtype=np.uint64)
     sizes = np.asarray(tree_sizes, dtype=np.int64)
-    assert off.shape[0] == int(sizes.sum()) + 1
+    if off.shape[0] != int(sizes.sum()) + 1:
+        raise ValueError("off must hold one entry per leaf plus one")
     d_arg = data if data.size else np.zeros(1, np.uint8)
     roots = np.zeros((sizes.shape[0], 32), np.uint8)
     lib = _load()
