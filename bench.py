@@ -293,7 +293,9 @@ def bench_serving(args) -> dict:
         for frac in args.loads:
             rate_tx = frac * ref
             rate_req = rate_tx / mean_size
-            count = int(min(args.max_requests, max(200, rate_req * args.point_seconds)))
+            # at least --min-requests per point (the low loads would otherwise
+            # see a few thousand), at most --max-requests
+            count = int(min(args.max_requests, max(args.min_requests, rate_req * args.point_seconds)))
             sizes, starts = requests(count, int(frac * 1000))
             gaps = rng.exponential(1.0 / rate_req, size=count)
             t0 = time.monotonic() + 0.05
@@ -674,6 +676,7 @@ def main() -> int:
     ap.add_argument("--inflight", type=int, default=4, help="serving: batches in flight")
     ap.add_argument("--sat-requests", type=int, default=20000)
     ap.add_argument("--max-requests", type=int, default=20000)
+    ap.add_argument("--min-requests", type=int, default=10000)
     ap.add_argument("--point-seconds", type=float, default=1.5)
     ap.add_argument("--loads", type=float, nargs="+",
                     default=[0.1, 0.18, 0.32, 0.5, 0.75, 0.9, 1.1, 1.5])
