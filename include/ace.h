@@ -208,8 +208,15 @@ ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blo
  *   derive_wgs_per_cu  workgroups per CU of the key derivation while it runs
  *                      beside the binning passes (keys derived in a binned
  *                      call); 0: one workgroup per 256 identities
+ *   wide_min_len       binned calls: messages of at least this many bytes are
+ *                      verified from their block's offsets instead of the
+ *                      32-bit length of the bin-order record.  Default and
+ *                      largest value 2^31 - 1 (the record's length limit);
+ *                      lower values change no result and only move messages
+ *                      onto that path (tests use them to reach it without
+ *                      2 GiB messages).
  * ace_set_tuning rejects workgroup counts outside 1..64 (derive_wgs_per_cu:
- * 0..64).
+ * 0..64) and wide_min_len outside 1..2^31 - 1.
  */
 typedef struct {
     uint64_t binned_min_tx;
@@ -217,6 +224,7 @@ typedef struct {
     uint32_t aux_wgs_per_cu;
     uint32_t auto_persistent;
     uint32_t derive_wgs_per_cu;
+    uint64_t wide_min_len;
 } ace_tuning;
 
 ACE_API int ace_get_tuning(ace_tuning *out);

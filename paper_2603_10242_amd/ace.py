@@ -68,7 +68,7 @@ class ace_merkle_tree(ctypes.Structure):
 class ace_tuning(ctypes.Structure):
     _fields_ = [("binned_min_tx", ctypes.c_uint64), ("verify_wgs_per_cu", ctypes.c_uint32),
                 ("aux_wgs_per_cu", ctypes.c_uint32), ("auto_persistent", ctypes.c_uint32),
-                ("derive_wgs_per_cu", ctypes.c_uint32)]
+                ("derive_wgs_per_cu", ctypes.c_uint32), ("wide_min_len", ctypes.c_uint64)]
 
 
 class ace_profile(ctypes.Structure):

@@ -76,6 +76,7 @@ ace_tuning g_tune = {
     /* aux_wgs_per_cu    */ 8,
     /* auto_persistent   */ 0,
     /* derive_wgs_per_cu */ 1,
+    /* wide_min_len      */ kRecMaxLen,
 };
 
 ace_tuning tuning()
@@ -487,7 +488,7 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
     if ((rc = launch_status("k_bin_scan launch"))) return rc;
     hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm, rec,
-                       pos_of);
+                       pos_of, tn.wide_min_len);
     if ((rc = launch_status("k_bin_scatter launch"))) return rc;
     if (fk && (rc = check_hip(hipStreamWaitEvent(s, fk->join, 0), "hipStreamWaitEvent"))) return rc;
     prof_mark(prof, 2, s);
@@ -598,6 +599,8 @@ ACE_API int ace_set_tuning(const ace_tuning *t)
     if (t->verify_wgs_per_cu < 1 || t->verify_wgs_per_cu > 64 || t->aux_wgs_per_cu < 1 ||
         t->aux_wgs_per_cu > 64 || t->derive_wgs_per_cu > 64)
         return fail(ACE_ERR_INVALID_ARG, "workgroups per CU must be in 1..64 (derive: 0..64)");
+    if (t->wide_min_len < 1 || t->wide_min_len > kRecMaxLen)
+        return fail(ACE_ERR_INVALID_ARG, "wide_min_len must be in 1..2^31 - 1");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune = *t;
     return ACE_OK;

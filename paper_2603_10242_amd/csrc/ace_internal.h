@@ -105,7 +105,8 @@ struct HkdfPrep {
 // One transaction in bin order, written by the scatter pass so that the
 // verify kernel reads contiguous records instead of gathering offsets and
 // identities from scattered lines.
-constexpr uint32_t kRecWide = 0xFFFFFFFFu;     // len: 2^31 - 1 bytes or more, re-read the offsets
+constexpr uint32_t kRecWide = 0xFFFFFFFFu;     // len: a wide message, re-read the offsets
+constexpr uint64_t kRecMaxLen = 0x7FFFFFFFu;   // messages this long or longer are always wide
 constexpr uint32_t kRecNearEnd = 0x80000000u;  // len flag: the block's message area ends within
                                                // kOverread bytes after this message
 constexpr uint32_t kRecInvalid = 0xFFFFFFFFu;  // id: the transaction cannot be valid

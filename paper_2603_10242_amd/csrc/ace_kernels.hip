@@ -487,7 +487,7 @@ __global__ void k_bin_scan(Ctrl *ctrl)
 __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_t n_id,
                                             unsigned long long *__restrict__ perm,
                                             TxRec *__restrict__ rec, uint32_t *__restrict__ pos_of,
-                                            uint32_t wg, uint32_t n_wg)
+                                            uint64_t wide_min, uint32_t wg, uint32_t n_wg)
 {
     constexpr int kPer = kTile / kWG;
     __shared__ uint32_t cnt[kBins];
@@ -512,7 +512,7 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_
                 const bool ok = a <= e && who < n_id;
                 const uint64_t L = ok ? e - a : 0;
                 r[k].addr = reinterpret_cast<uint64_t>(d.msg + a);
-                r[k].len = L >= (kRecWide >> 1) ? kRecWide
+                r[k].len = L >= wide_min ? kRecWide
                                                 : (uint32_t)L | (e + kOverread <= area_end ? 0u : kRecNearEnd);
                 r[k].id = ok ? who : kRecInvalid;
                 bins[k] = bin_of_length(L);
@@ -541,9 +541,10 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_
 __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint32_t n_id,
                                                      unsigned long long *__restrict__ perm,
                                                      TxRec *__restrict__ rec,
-                                                     uint32_t *__restrict__ pos_of)
+                                                     uint32_t *__restrict__ pos_of, uint64_t wide_min)
 {
-    bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, blockIdx.x, gridDim.x);
+    bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, wide_min < kRecMaxLen ? wide_min : kRecMaxLen,
+                blockIdx.x, gridDim.x);
 }
 
 // Most wave tiles a persistent verify wave takes per atomic grab.
@@ -561,7 +562,7 @@ __device__ __forceinline__ bool binned_tx(const Batch &bt, const Totals &T, cons
 {
     const uint32_t b = (uint32_t)(e >> 40);
     const uint64_t i = e & ((1ull << 40) - 1);
-    if (r.len == kRecWide) return load_tx<ATTEST>(get_block(bt, T, b), i, ks, t);  // 2 GiB or more
+    if (r.len == kRecWide) return load_tx<ATTEST>(get_block(bt, T, b), i, ks, t);  // a wide message
     const bool live = r.id != kRecInvalid;
     const uint32_t who = live ? r.id : 0u;
     t.msg = reinterpret_cast<const uint8_t *>(r.addr);

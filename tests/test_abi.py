@@ -218,6 +218,12 @@ def test_tuning_roundtrip_and_limits(lib):
         assert ace.get_tuning()["derive_wgs_per_cu"] == 0
         with pytest.raises(ace.AceError):
             ace.set_tuning(derive_wgs_per_cu=65)
+        assert old["wide_min_len"] == 2**31 - 1     # only messages the record cannot hold
+        ace.set_tuning(wide_min_len=1)
+        assert ace.get_tuning()["wide_min_len"] == 1
+        for bad in (0, 2**31, 2**40):
+            with pytest.raises(ace.AceError):
+                ace.set_tuning(wide_min_len=bad)
     finally:
         ace.set_tuning(**old)
     assert ace.get_tuning() == old

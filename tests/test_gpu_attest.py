@@ -124,6 +124,29 @@ def test_unregistered_ids_and_bad_offsets(ace):
         assert np.array_equal(mask, omask)
 
 
+@pytest.mark.parametrize("kind", ["midstate", "rev"])
+def test_wide_records_read_offsets(ace, kind):
+    """Paper form with wide_min_len lowered to 142 bytes (the median of these
+    130-154 byte payloads): payloads of at least that length are read through
+    their block's offsets, the rest through their bin-order records; results
+    as the oracle's in both binned launch forms."""
+    note("paper-form wide records keys=%s" % kind)
+    w = W.paper_attestations(n=3000, n_id=256, n_invalid=300, seed=W.SEED_BASE + 500)
+    ids = w.ids.copy()
+    poff = w.poff.copy()
+    ids[7] = w.n_id
+    poff[20], poff[21] = poff[21], poff[20]
+    omask, ocount = oracle.verify_attest(w.keys, w.payload, poff, ids, w.att)
+    old = ace.get_tuning()
+    try:
+        ace.set_tuning(wide_min_len=142)
+        for mode in ("binned", "binned-persistent"):
+            mask, count = run(ace, w, kind, MODES[mode], poff=poff, ids=ids)
+            assert count == ocount and np.array_equal(mask, omask), mode
+    finally:
+        ace.set_tuning(**old)
+
+
 def test_multi_block(ace):
     """Several paper-form blocks in one call; bits land in their own blocks."""
     import torch

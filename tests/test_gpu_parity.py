@@ -297,6 +297,33 @@ def test_unregistered_ids_and_bad_offsets(ace):
             assert count == ocount and np.array_equal(mask, omask), (mode, name)
 
 
+@pytest.mark.parametrize("wide_min", [1, 150, 700])
+def test_wide_records_read_offsets(ace, wide_min):
+    """Binned calls verify a message of at least wide_min_len bytes from its
+    block's offsets instead of its bin-order record (by default only messages
+    of 2 GiB or more, whose length the record cannot hold).  Lowered, the
+    tuning moves ordinary messages (96-512 bytes here) onto that path, which
+    must change no result: unregistered identities and decreasing offsets
+    included, both binned launch forms, midstates and keys derived in the
+    call.  700 is the control with no wide message."""
+    note("wide records, wide_min_len=%d" % wide_min)
+    w = W.subset(W.config2(), 0, 5000)
+    ids = w.ids.copy()
+    off = w.off.copy()
+    ids[[3, 100, 4999]] = [w.n_id, 0xFFFFFFFF, w.n_id + 5]
+    off[200], off[201] = off[201], off[200]
+    omask, ocount = oracle_result(w, ids=ids, off=off)
+    old = ace.get_tuning()
+    try:
+        ace.set_tuning(wide_min_len=wide_min)
+        for mode in ("binned", "binned-persistent"):
+            for name, ks in keysets(ace, w).items():
+                mask, count = run(ace, w, ks, MODES[mode], ids=ids, off=off)
+                assert count == ocount and np.array_equal(mask, omask), (mode, name)
+    finally:
+        ace.set_tuning(**old)
+
+
 def test_all_valid_and_all_invalid(ace):
     w = W.generate("clean", 5, n=3000, n_id=100, lengths=lambda r, n: r.integers(0, 700, size=n))
     for mode in MODES.values():
