@@ -124,6 +124,58 @@ def test_unregistered_ids_and_bad_offsets(ace):
         assert np.array_equal(mask, omask)
 
 
+def test_every_single_bit_flip_is_rejected(ace):
+    """Tamper invariants of the paper form on the GPU: for three attestations
+    (payloads of 55, 64 and 200 bytes), every single-bit flip of the payload,
+    of the 72-byte record (obj_hash, domain, credential) and of the identity's
+    root entropy is a transaction of one batch; only the three untouched ones
+    may pass, in every launch mode, with midstates and keys derived in the
+    call."""
+    import torch
+    note("paper-form every single-bit flip")
+    w = W.paper_attestations(n=3, n_id=3, lengths=np.array([55, 64, 200]), id_dist="uniform",
+                             n_invalid=0, seed=W.SEED_BASE + 600)
+    assert w.truth.all()
+    rev = [w.rev]
+    for j in range(3):                              # identity 3 + 256 j + b: REV_j, bit b flipped
+        fl = np.repeat(w.rev[j:j + 1], 256, axis=0)
+        fl[np.arange(256), np.arange(256) // 8] ^= (1 << (np.arange(256) % 8)).astype(np.uint8)
+        rev.append(fl)
+    rev = np.concatenate(rev)
+    parts, ids, recs, truth = [], [], [], []
+    for k in range(3):
+        pl = w.payload[int(w.poff[k]):int(w.poff[k + 1])]
+        j = int(w.ids[k])
+        parts.append(pl); ids.append(j); recs.append(w.att[k]); truth.append(True)
+        for b in range(8 * pl.size):                                                # payload flips
+            f = pl.copy(); f[b // 8] ^= 1 << (b % 8)
+            parts.append(f); ids.append(j); recs.append(w.att[k]); truth.append(False)
+        for b in range(8 * 72):                                                     # record flips
+            a = w.att[k].copy(); a[b // 8] ^= 1 << (b % 8)
+            parts.append(pl); ids.append(j); recs.append(a); truth.append(False)
+        for b in range(256):                                                        # root-entropy flips
+            parts.append(pl); ids.append(3 + 256 * j + b); recs.append(w.att[k]); truth.append(False)
+    lead = 3                                                                        # misaligned start
+    buf = np.concatenate([np.zeros(lead, np.uint8)] + parts)
+    poff = np.zeros(len(parts) + 1, np.uint64)
+    poff[1:] = np.cumsum([p.size for p in parts])
+    poff += lead
+    ids = np.array(ids, np.uint32)
+    recs = np.stack(recs)
+    truth = np.array(truth)
+    keys = oracle.derive_keys(rev, w.domain, w.info, 8)
+    omask, ocount = oracle.verify_attest(keys, buf, poff, ids, recs, 8)
+    assert ocount == 3 and np.array_equal(omask, W.pack_bits(truth))
+    devrev = ace.to_device(rev)
+    for mode in MODES.values():
+        for ks in (ace.midstate_keyset(devrev, w.domain, w.info), ace.rev_keyset(devrev, w.domain, w.info)):
+            blk = ace.upload_block(buf, poff, ids, recs, record_bytes=72)
+            ace.verify_attestations(ks, [blk], flags=mode)
+            torch.cuda.synchronize()
+            mask, count = blk.result()
+            assert count == 3 and np.array_equal(mask, omask), mode
+
+
 @pytest.mark.parametrize("kind", ["midstate", "rev"])
 def test_wide_records_read_offsets(ace, kind):
     """Paper form with wide_min_len lowered to 142 bytes (the median of these

@@ -297,6 +297,62 @@ def test_unregistered_ids_and_bad_offsets(ace):
             assert count == ocount and np.array_equal(mask, omask), (mode, name)
 
 
+def test_every_single_bit_flip_is_rejected(ace):
+    """Tamper invariants on the GPU: for three messages (55, 64 and 200 bytes,
+    one padding case each), every single-bit flip of the message, of the
+    credential and of the identity's root entropy is a transaction of one
+    batch; only the three untouched transactions may pass, in every launch
+    mode, with midstates and with keys derived in the call."""
+    note("every single-bit flip")
+    r = np.random.Generator(np.random.PCG64(2024))
+    msgs = [r.integers(0, 256, size=L, dtype=np.uint8) for L in (55, 64, 200)]
+    base_rev = r.integers(0, 256, size=(3, 32), dtype=np.uint8)
+    rev = [base_rev]
+    for j in range(3):                               # identity 3 + 256 j + b: REV_j, bit b flipped
+        fl = np.repeat(base_rev[j:j + 1], 256, axis=0)
+        fl[np.arange(256), np.arange(256) // 8] ^= (1 << (np.arange(256) % 8)).astype(np.uint8)
+        rev.append(fl)
+    rev = np.concatenate(rev)
+    salt = r.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+    keys = W.client_keys(rev, salt, W.INFO_16)
+    one_off = np.array([0, 0], np.uint64)
+    tags = [W.client_sign(keys, m, one_off + np.array([0, m.size], np.uint64), np.array([j], np.uint32))[0]
+            for j, m in enumerate(msgs)]
+    parts, ids, tag_rows = [], [], []
+    for j, m in enumerate(msgs):
+        parts.append(m); ids.append(j); tag_rows.append(tags[j])                  # untouched
+        for b in range(8 * m.size):                                                 # message flips
+            f = m.copy(); f[b // 8] ^= 1 << (b % 8)
+            parts.append(f); ids.append(j); tag_rows.append(tags[j])
+        for b in range(256):                                                        # credential flips
+            t = tags[j].copy(); t[b // 8] ^= 1 << (b % 8)
+            parts.append(m); ids.append(j); tag_rows.append(t)
+        for b in range(256):                                                        # root-entropy flips
+            parts.append(m); ids.append(3 + 256 * j + b); tag_rows.append(tags[j])
+    lead = 1                                                                        # misaligned start
+    buf = np.concatenate([np.zeros(lead, np.uint8)] + parts)
+    off = np.zeros(len(parts) + 1, np.uint64)
+    off[1:] = np.cumsum([p.size for p in parts])
+    off += lead
+    ids = np.array(ids, np.uint32)
+    tag_rows = np.stack(tag_rows)
+    truth = np.zeros(len(parts), bool)
+    firsts = np.cumsum([0] + [1 + 8 * m.size + 512 for m in msgs])[:3]
+    truth[firsts] = True
+    omask, ocount = oracle.verify_batch(oracle.derive_keys(rev, salt, W.INFO_16, 8), buf, off, ids,
+                                        tag_rows, 8)
+    assert ocount == 3 and np.array_equal(omask, W.pack_bits(truth))
+    import torch
+    devrev = ace.to_device(rev)
+    for mode in MODES.values():
+        for ks in (ace.midstate_keyset(devrev, salt, W.INFO_16), ace.rev_keyset(devrev, salt, W.INFO_16)):
+            blk = ace.upload_block(buf, off, ids, tag_rows)
+            ace.verify_batch(ks, [blk], flags=mode)
+            torch.cuda.synchronize()
+            mask, count = blk.result()
+            assert count == 3 and np.array_equal(mask, omask), mode
+
+
 @pytest.mark.parametrize("wide_min", [1, 150, 700])
 def test_wide_records_read_offsets(ace, wide_min):
     """Binned calls verify a message of at least wide_min_len bytes from its
