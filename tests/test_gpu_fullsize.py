@@ -1,8 +1,10 @@
 """Parity at the benchmarks' full sizes, in the launch configuration bench.py
-times (binned, keys derived in the call, the saved launch tuning): the whole
-bitmask against the generator's truth mask, and a sample of transactions
-checked one by one against the CPU oracle (which cannot verify 16M
-transactions in a test's time).  Integer work: tolerance 0."""
+times (binned, keys derived in the call, the saved launch tuning): every
+bitmask word, count and root against the CPU oracle, run multi-threaded over
+the whole workload (the C oracle verifies the 16M batch in a few seconds on
+the host's cores), and against the generator's truth mask.  Integer work:
+tolerance 0."""
+import os
 import sys
 
 import numpy as np
@@ -13,7 +15,7 @@ from paper_2603_10242_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 
-N_SAMPLE = 20000
+NT = max(1, min(16, os.cpu_count() or 1))  # oracle threads
 
 
 def note(msg):
@@ -32,29 +34,7 @@ def ace(need_gpu):
     return A
 
 
-def gather(data, off, idx):
-    """The records idx of a packed array, packed again (offsets from 0)."""
-    lens = (off[idx + 1] - off[idx]).astype(np.int64)
-    noff = np.zeros(idx.size + 1, dtype=np.uint64)
-    noff[1:] = np.cumsum(lens)
-    out = np.concatenate([data[int(off[i]):int(off[i + 1])] for i in idx]) if idx.size else data[:0]
-    return out, noff
-
-
-def sample(n, seed, invalid, k=N_SAMPLE):
-    """About k indices: random ones, the first k // 4 invalid ones, and the
-    last transaction (ragged tail)."""
-    r = np.random.Generator(np.random.PCG64(seed))
-    bad = np.flatnonzero(invalid)[: k // 4]
-    idx = np.unique(np.concatenate([r.choice(n, k - bad.size - 1, replace=False), bad, [n - 1]]))
-    return idx.astype(np.int64)
-
-
-def bit(mask, i):
-    return (mask[i >> 5] >> (i & 31)) & 1
-
-
-def test_sweep_16M_keys_in_call_sampled(ace):
+def test_sweep_16M_keys_in_call(ace):
     import torch
     note("full size: 16M-tx sweep, 1M identities, binned, keys derived in the call")
     w = W.config3(n=16 << 20, n_id=1 << 20)
@@ -64,22 +44,15 @@ def test_sweep_16M_keys_in_call_sampled(ace):
     ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED)
     torch.cuda.synchronize()
     mask, count = blk.result()
-    assert count == int(w.truth.sum())
+    note("oracle on all %d transactions, %d threads" % (w.n, NT))
+    keys = oracle.derive_keys(w.rev, w.salt, w.info, NT)
+    omask, ocount = oracle.verify_batch(keys, w.msg, w.off, w.ids, w.tags, NT)
+    assert count == ocount == int(w.truth.sum()) and ocount < w.n
+    assert np.array_equal(mask, omask)
     assert np.array_equal(mask, w.truth_bitmask())
-    idx = sample(w.n, 71, ~w.truth)
-    note("oracle on %d sampled transactions" % idx.size)
-    ids = w.ids[idx]
-    uid, local = np.unique(ids, return_inverse=True)
-    keys = oracle.derive_keys(w.rev[uid], w.salt, w.info, 8)
-    msg, off = gather(w.msg, w.off, idx)
-    omask, ocount = oracle.verify_batch(keys, msg, off, local.astype(np.uint32), w.tags[idx], 8)
-    got = np.array([bit(mask, int(i)) for i in idx], dtype=np.uint32)
-    want = np.array([bit(omask, k) for k in range(idx.size)], dtype=np.uint32)
-    assert np.array_equal(got, want)
-    assert ocount == int(want.sum()) and ocount < idx.size  # the sample holds invalid ones
 
 
-def test_paper_form_16M_keys_in_call_sampled(ace):
+def test_paper_form_16M_keys_in_call(ace):
     import torch
     note("full size: 16M paper-form attestations, 1M identities, binned, keys in the call")
     a = W.paper_attestations(n=16 << 20, n_id=1 << 20, id_dist="uniform", p_invalid=0.005)
@@ -89,21 +62,15 @@ def test_paper_form_16M_keys_in_call_sampled(ace):
     ace.verify_attestations(ks, [blk], flags=ace.ACE_BUCKETED)
     torch.cuda.synchronize()
     mask, count = blk.result()
-    assert count == int(a.truth.sum())
+    note("oracle on all %d attestations, %d threads" % (a.n, NT))
+    keys = oracle.derive_keys(a.rev, a.domain, a.info, NT)
+    omask, ocount = oracle.verify_attest(keys, a.payload, a.poff, a.ids, a.att, NT)
+    assert count == ocount == int(a.truth.sum()) and ocount < a.n
+    assert np.array_equal(mask, omask)
     assert np.array_equal(mask, a.truth_bitmask())
-    idx = sample(a.n, 72, ~a.truth)
-    note("oracle on %d sampled attestations" % idx.size)
-    uid, local = np.unique(a.ids[idx], return_inverse=True)
-    keys = oracle.derive_keys(a.rev[uid], a.domain, a.info, 8)
-    payload, poff = gather(a.payload, a.poff, idx)
-    omask, ocount = oracle.verify_attest(keys, payload, poff, local.astype(np.uint32), a.att[idx], 8)
-    got = np.array([bit(mask, int(i)) for i in idx], dtype=np.uint32)
-    want = np.array([bit(omask, k) for k in range(idx.size)], dtype=np.uint32)
-    assert np.array_equal(got, want)
-    assert ocount == int(want.sum()) and ocount < idx.size
 
 
-def test_merkle_256_blocks_sampled_trees(ace):
+def test_merkle_256_blocks(ace):
     import torch
     note("full size: Merkle roots of the batching workload's 256 blocks of 72-byte records")
     sizes = W.batching_block_sizes()
@@ -120,15 +87,12 @@ def test_merkle_256_blocks_sampled_trees(ace):
     ace.merkle_roots(trees)
     torch.cuda.synchronize()
     got = roots.cpu().numpy()
-    firsts = np.concatenate([[0], np.cumsum(sizes)])
-    picks = sorted({0, 1, int(np.argmax(sizes)), int(np.argmin(sizes)), sizes.size // 2, sizes.size - 1})
-    for b in picks:
-        lo, hi = int(firsts[b]), int(firsts[b + 1])
-        want = oracle.merkle_roots(data[72 * lo:72 * hi], off[lo:hi + 1] - off[lo], [hi - lo])
-        assert np.array_equal(got[b], want[0]), b
+    note("oracle on all %d trees (%d leaves)" % (sizes.size, n))
+    want = oracle.merkle_roots(data, off, sizes)
+    assert np.array_equal(got, want)
 
 
-def test_hash_chain_262144_segments_sampled(ace):
+def test_hash_chain_262144_segments(ace):
     import torch
     note("full size: 262,144 hash-chain segments of 1,024 hashes")
     w = W.poh_segments(n=1 << 18, steps=1024, step_errors=False)
@@ -138,11 +102,8 @@ def test_hash_chain_262144_segments_sampled(ace):
     ace.poh_verify(s, e, 1024, mask, cnt)  # uniform steps, as the benchmark launches it
     torch.cuda.synchronize()
     m = mask.cpu().numpy().view(np.uint32)
-    assert int(cnt.item()) == int(w.truth.sum())
+    note("oracle on all %d segments, %d threads" % (w.n, NT))
+    omask, ocount = oracle.poh_verify(w.start, w.end, w.steps, NT)
+    assert int(cnt.item()) == ocount == int(w.truth.sum()) and ocount < w.n
+    assert np.array_equal(m, omask)
     assert np.array_equal(m, w.truth_bitmask())
-    idx = sample(w.n, 73, ~w.truth, 4096)
-    omask, ocount = oracle.poh_verify(w.start[idx], w.end[idx], w.steps[idx], 8)
-    got = np.array([bit(m, int(i)) for i in idx], dtype=np.uint32)
-    want = np.array([bit(omask, k) for k in range(idx.size)], dtype=np.uint32)
-    assert np.array_equal(got, want)
-    assert ocount == int(want.sum()) and ocount < idx.size
