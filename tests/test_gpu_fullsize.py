@@ -70,6 +70,90 @@ def test_paper_form_16M_keys_in_call(ace):
     assert np.array_equal(mask, a.truth_bitmask())
 
 
+def test_batching_256_blocks_graph_replay(ace):
+    """The batching workload (256 blocks, 7.66M transactions, Zipf identities,
+    resident midstates) in one captured replay and in one eager multi-block
+    call: every block's bitmask and count against the oracle's for that
+    block."""
+    import torch
+    note("full size: batching workload, 256 blocks in one graph replay")
+    w = W.config4()
+    edges = np.concatenate([[0], np.cumsum(w.block_sizes)])
+    d_msg = ace.to_device(w.msg)
+    ks = ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info)
+    note("oracle on all %d transactions, %d threads" % (w.n, NT))
+    keys = oracle.derive_keys(w.rev, w.salt, w.info, NT)
+    want = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        off = w.off[a:b + 1] - w.off[a]
+        want.append(oracle.verify_batch(keys, w.msg[int(w.off[a]):int(w.off[b])], off, w.ids[a:b],
+                                        w.tags[a:b], NT))
+    g = ace.Graph(ks, max_blocks=len(edges) - 1, max_tx=w.n)
+    try:
+        for form in ("graph", "eager"):
+            blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
+                      for a, b in zip(edges[:-1], edges[1:])]
+            if form == "graph":
+                g.launch(blocks)
+            else:
+                ace.verify_batch(ks, blocks)
+            torch.cuda.synchronize()
+            for k, (blk, (omask, ocount)) in enumerate(zip(blocks, want)):
+                mask, count = blk.result()
+                a, b = int(edges[k]), int(edges[k + 1])
+                assert count == ocount == int(w.truth[a:b].sum()), (form, k)
+                assert np.array_equal(mask, omask), (form, k)
+    finally:
+        g.close()
+
+
+def test_serving_full_size_requests(ace):
+    """Serving at the benchmark's scale: the 4M-identity midstate cache
+    resident, 3,000 requests of lognormal(1,000, 1.5) sizes in [1, 50,000]
+    cut from the 4M-transaction pool and submitted from 8 threads as a
+    backlog (continuous batching, 4 batches in flight, the benchmark's arena
+    and staging sizes): every request's bitmask and count against the
+    oracle's for its range."""
+    import threading
+    import torch
+    note("full size: serving, 3,000 requests from a 4M-transaction pool, 4M identities")
+    pool = W.config5_pool()
+    ks = ace.midstate_keyset(ace.to_device(pool.rev), pool.salt, pool.info)
+    arena = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    st = ace.Stream.create(ks, arena, staging_bytes=2048 << 20, max_inflight=4)
+    sizes = W.serving_request_sizes(3000)
+    starts = np.random.Generator(np.random.PCG64(55)).integers(0, pool.n - sizes)
+    reqs = [(int(a), int(a + z)) for a, z in zip(starts, sizes)]
+    tickets = [None] * len(reqs)
+
+    def client(t0):
+        for k in range(t0, len(reqs), 8):
+            lo, hi = reqs[k]
+            tickets[k] = st.submit(pool.msg, pool.off[lo:hi + 1], pool.ids[lo:hi], pool.tags[lo:hi])
+
+    threads = [threading.Thread(target=client, args=(t,)) for t in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert all(t is not None for t in tickets)
+    note("oracle on all %d requests (%d transactions), %d threads" % (len(reqs), int(sizes.sum()), NT))
+    keys = oracle.derive_keys(pool.rev, pool.salt, pool.info, NT)
+    try:
+        for (lo, hi), t in zip(reqs, tickets):
+            mask, count = st.result(t)
+            omask, ocount = oracle.verify_batch(keys, pool.msg, pool.off[lo:hi + 1], pool.ids[lo:hi],
+                                                pool.tags[lo:hi], NT)
+            assert count == ocount == int(pool.truth[lo:hi].sum()), (lo, hi)
+            assert np.array_equal(mask, omask), (lo, hi)
+        stats = st.stats()
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        assert stats["max_batch_requests"] > 1  # requests were merged into batches
+    finally:
+        st.close()
+
+
 def test_merkle_256_blocks(ace):
     import torch
     note("full size: Merkle roots of the batching workload's 256 blocks of 72-byte records")
