@@ -239,7 +239,8 @@ ACE_API int ace_set_tuning(const ace_tuning *t);
  * Every grid is fixed: the binned verify kernel is launched for the largest
  * batch (surplus waves exit at once) or, with ACE_PERSISTENT, as the
  * persistent kernel; the in-order form (flag ACE_ORDERED) is a grid-stride
- * kernel.
+ * kernel.  The launch tuning in force at ace_graph_create is captured with
+ * the graph; later ace_set_tuning calls do not change its replays.
  *   d_workspace  at least ace_graph_workspace_size() bytes, 256-byte aligned,
  *                owned by the graph until ace_graph_destroy.
  * ace_graph_launch enqueues one replay on `stream` for the given blocks (the
