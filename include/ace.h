@@ -322,8 +322,13 @@ ACE_API int ace_stream_destroy(ace_stream *s);
  * allocated here, and each batch's blocks are verified by calling `fn` (for
  * example a CPU reference) -- so the queue, admission and retirement logic
  * runs without a GPU.  fail_after = k > 0 makes the k-th batch fail as a
- * device error would; only that batch's requests fail.
+ * device error would; only that batch's requests fail.  With the flag
+ * ACE_STREAM_HOST_FAIL_LAUNCH the k-th batch's verify call itself returns the
+ * error (after its input copies were queued), which takes the engine's
+ * launch-failure path: the slot is drained before the batch's memory is
+ * reused.
  */
+#define ACE_STREAM_HOST_FAIL_LAUNCH 0x100u
 typedef int (*ace_host_verify_fn)(void *user, const uint8_t *msg, const uint64_t *off,
                                   const uint32_t *id, const uint8_t *tag, uint64_t n_tx,
                                   uint32_t *bitmask_out, uint64_t *count_out);

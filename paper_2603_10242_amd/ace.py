@@ -440,6 +440,7 @@ class Graph:
 # ------------------------------------------------------------------------------ serving
 ACE_NONBLOCK = 0x1
 ACE_STREAM_PLAIN = 0x1
+ACE_STREAM_HOST_FAIL_LAUNCH = 0x100
 
 
 class ace_stream_stats(ctypes.Structure):
@@ -503,8 +504,11 @@ class Stream:
 
     @classmethod
     def create_host(cls, verify, arena_bytes: int, staging_bytes: int, max_inflight: int = 4,
-                    plain: bool = False, fail_after: int = 0) -> "Stream":
-        """Host backend for tests: verify(msg, off, ids, tags) -> (bitmask u32[], count)."""
+                    plain: bool = False, fail_after: int = 0,
+                    fail_at_launch: bool = False) -> "Stream":
+        """Host backend for tests: verify(msg, off, ids, tags) -> (bitmask u32[], count).
+        fail_after = k makes the k-th batch fail when it completes or, with
+        fail_at_launch, in its launch call."""
         lib = load()
         _stream_protos(lib)
 
@@ -532,9 +536,10 @@ class Stream:
 
         fn = HOST_VERIFY_FN(cb)
         h = ctypes.c_void_p()
-        _check(lib.ace_stream_create_host(fn, None, arena_bytes, staging_bytes, max_inflight,
-                                          ACE_STREAM_PLAIN if plain else 0, fail_after,
-                                          ctypes.byref(h)))
+        flags = (ACE_STREAM_PLAIN if plain else 0) | (ACE_STREAM_HOST_FAIL_LAUNCH if fail_at_launch
+                                                       else 0)
+        _check(lib.ace_stream_create_host(fn, None, arena_bytes, staging_bytes, max_inflight, flags,
+                                          fail_after, ctypes.byref(h)))
         return cls(h, [fn])
 
     def submit(self, msg: np.ndarray, off: np.ndarray, ids: np.ndarray, tags: np.ndarray,

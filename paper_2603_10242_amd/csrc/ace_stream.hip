@@ -115,10 +115,13 @@ class Backend {
     virtual uint8_t *arena() = 0;
     virtual int begin_slot(int slot) = 0;
     virtual int h2d(int slot, void *dst, const void *src, size_t n) = 0;
+    // `flags` is chosen once per batch and passed to both calls, so the
+    // workspace sized for a batch is the one its verify call needs
     virtual int verify(int slot, const ace_block *blocks, uint32_t n_blocks, void *ws,
-                       size_t ws_bytes) = 0;
-    virtual size_t ws_size(const ace_block *blocks, uint32_t n_blocks) = 0;
-    // workspace of a batch holding only one request of n transactions
+                       size_t ws_bytes, uint32_t flags) = 0;
+    virtual size_t ws_size(const ace_block *blocks, uint32_t n_blocks, uint32_t flags) = 0;
+    // largest workspace a batch holding only one request of n transactions
+    // can need (the binned layout contains the in-order one)
     size_t ws_bound(uint64_t n)
     {
         ace_block b;
@@ -131,12 +134,16 @@ class Backend {
         b.d_bitmask_out = reinterpret_cast<uint32_t *>(fake);
         b.d_count_out = reinterpret_cast<uint64_t *>(fake);
         b.n_tx = n;
-        return ws_size(&b, 1);
+        return ws_size(&b, 1, ACE_BUCKETED);
     }
     virtual int d2h(int slot, void *dst, const void *src, size_t n) = 0;
     virtual int end_slot(int slot) = 0;
     virtual int query(int slot) = 0;  // 1 done, 0 running, < 0 failed
-    virtual int wait(int slot) = 0;
+    virtual int wait(int slot) = 0;   // until the slot's last completed batch is done
+    // until everything queued on the slot so far has finished, including work
+    // of a batch whose launch sequence failed part way (its copies may still
+    // be writing into the arena)
+    virtual int drain(int slot) = 0;
 };
 
 // ---- HIP backend -------------------------------------------------------------------------
@@ -168,13 +175,14 @@ class HipBackend : public Backend {
     {
         return check_hip(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, streams_[slot]), "hipMemcpyAsync H2D");
     }
-    size_t ws_size(const ace_block *blocks, uint32_t n_blocks) override
+    size_t ws_size(const ace_block *blocks, uint32_t n_blocks, uint32_t flags) override
     {
-        return ace_verify_workspace_size(&keys_, blocks, n_blocks, 0);
+        return ace_verify_workspace_size(&keys_, blocks, n_blocks, flags);
     }
-    int verify(int slot, const ace_block *blocks, uint32_t n_blocks, void *ws, size_t ws_bytes) override
+    int verify(int slot, const ace_block *blocks, uint32_t n_blocks, void *ws, size_t ws_bytes,
+               uint32_t flags) override
     {
-        return ace_verify_batch(&keys_, blocks, n_blocks, ws, ws_bytes, 0, streams_[slot]);
+        return ace_verify_batch(&keys_, blocks, n_blocks, ws, ws_bytes, flags, streams_[slot]);
     }
     int d2h(int slot, void *dst, const void *src, size_t n) override
     {
@@ -189,6 +197,7 @@ class HipBackend : public Backend {
         return check_hip(e, "hipEventQuery");
     }
     int wait(int slot) override { return check_hip(hipEventSynchronize(done_[slot]), "hipEventSynchronize"); }
+    int drain(int slot) override { return check_hip(hipStreamSynchronize(streams_[slot]), "hipStreamSynchronize"); }
 
   private:
     ace_keyset keys_;
@@ -201,8 +210,10 @@ class HipBackend : public Backend {
 // ---- host backend (tests) ----------------------------------------------------------------
 class HostBackend : public Backend {
   public:
-    HostBackend(ace_host_verify_fn fn, void *user, size_t arena_bytes, uint32_t fail_after)
-        : fn_(fn), user_(user), mem_(arena_bytes), fail_after_(fail_after), slot_status_(64, 1)
+    HostBackend(ace_host_verify_fn fn, void *user, size_t arena_bytes, uint32_t fail_after,
+                bool fail_at_launch)
+        : fn_(fn), user_(user), mem_(arena_bytes), fail_after_(fail_after),
+          fail_at_launch_(fail_at_launch), slot_status_(64, 1)
     {
     }
     uint8_t *arena() override { return mem_.data(); }
@@ -216,10 +227,13 @@ class HostBackend : public Backend {
         memcpy(dst, src, n);
         return ACE_OK;
     }
-    size_t ws_size(const ace_block *, uint32_t) override { return 256; }
-    int verify(int slot, const ace_block *blocks, uint32_t n_blocks, void *, size_t) override
+    size_t ws_size(const ace_block *, uint32_t, uint32_t) override { return 256; }
+    int verify(int slot, const ace_block *blocks, uint32_t n_blocks, void *, size_t, uint32_t) override
     {
         ++launches_;
+        if (fail_after_ && launches_ == fail_after_ && fail_at_launch_)
+            return fail(ACE_ERR_DEVICE, "injected launch failure on launch %llu",
+                        (unsigned long long)launches_);
         if (fail_after_ && launches_ == fail_after_) {
             slot_status_[slot] = fail(ACE_ERR_DEVICE, "injected device failure on launch %llu",
                                       (unsigned long long)launches_);
@@ -241,12 +255,20 @@ class HostBackend : public Backend {
     int end_slot(int) override { return ACE_OK; }
     int query(int slot) override { return slot_status_[slot]; }
     int wait(int slot) override { return slot_status_[slot] < 0 ? slot_status_[slot] : ACE_OK; }
+    int drain(int) override
+    {
+        ++drains_;
+        return ACE_OK;
+    }
+    uint64_t drains() const { return drains_; }
 
   private:
     ace_host_verify_fn fn_;
     void *user_;
     std::vector<uint8_t> mem_;
     uint32_t fail_after_;
+    bool fail_at_launch_;
+    uint64_t drains_ = 0;
     uint64_t launches_ = 0;
     std::vector<int> slot_status_;
 };
@@ -256,6 +278,19 @@ double now_s()
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
+
+// A client call inside the engine: counted under the lock so that
+// ace_stream_destroy frees nothing while one is still running.
+struct InCall {
+    std::condition_variable &cv;
+    uint32_t &n;
+    // constructed and destroyed with the engine's lock held
+    InCall(std::condition_variable &cv_, uint32_t &n_) : cv(cv_), n(n_) { ++n; }
+    ~InCall()
+    {
+        if (--n == 0) cv.notify_all();
+    }
+};
 
 constexpr uint32_t kMaxBatchRequests = 4096;
 // A batch is capped so that its upload stays around a millisecond: requests
@@ -287,6 +322,7 @@ struct ace_stream {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
+    uint32_t in_calls = 0;  // client calls inside the engine (destroy waits for 0)
     struct Slot {
         bool busy = false;
         bool launching = false;
@@ -376,16 +412,22 @@ bool admit(ace_stream *s)
         ++m;
     }
     // largest prefix whose arena range (inputs, outputs, workspace) and result
-    // area fit now
+    // area fit now.  The launch form (in-order or binned) is fixed here from
+    // one reading of the tuning and passed to both the workspace size and the
+    // verify call, so a tuning change in between cannot make them disagree.
+    const ace_tuning tn = tuning();
     std::vector<ace_block> blocks;
     size_t arena_off = 0, arena_bytes = 0, in_total = 0, out_total = 0;
+    uint32_t vflags = ACE_ORDERED;
     while (m > 0) {
         in_total = out_total = 0;
+        uint64_t m_tx = 0;
         blocks.assign(m, ace_block{});
         for (size_t k = 0; k < m; ++k) {
             const Request *r = s->pending[k];
             in_total += r->lay.in_bytes;
             out_total += r->lay.out_bytes;
+            m_tx += r->n;
             ace_block &bk = blocks[k];
             const uintptr_t fake = 0x1000;  // sizes only: real addresses are set below
             bk.d_msg = reinterpret_cast<const uint8_t *>(fake);
@@ -396,7 +438,9 @@ bool admit(ace_stream *s)
             bk.d_count_out = reinterpret_cast<uint64_t *>(fake);
             bk.n_tx = r->n;
         }
-        const size_t ws = align_up(s->be->ws_size(blocks.data(), (uint32_t)m), 256);
+        vflags = m_tx >= tn.binned_min_tx ? (ACE_BUCKETED | (tn.auto_persistent ? ACE_PERSISTENT : 0u))
+                                          : ACE_ORDERED;
+        const size_t ws = align_up(s->be->ws_size(blocks.data(), (uint32_t)m, vflags), 256);
         arena_bytes = in_total + align_up(out_total, 256) + ws;
         if (ws && s->arena_alloc.alloc(arena_bytes, arena_off)) break;
         m = m > 1 ? m - std::max<size_t>(1, m / 4) : 0;
@@ -451,10 +495,14 @@ bool admit(ace_stream *s)
         rc = s->be->h2d(free_slot, base + in_pos[k], staging + batch[k]->stage_off, bytes);
         k = j;
     }
-    if (!rc) rc = s->be->verify(free_slot, blocks.data(), (uint32_t)m, ws_ptr, ws_bytes);
+    if (!rc) rc = s->be->verify(free_slot, blocks.data(), (uint32_t)m, ws_ptr, ws_bytes, vflags);
     if (!rc) rc = s->be->d2h(free_slot, sl.result, out_base, out_total);
     if (!rc) rc = s->be->end_slot(free_slot);
-    if (rc) s->be->wait(free_slot);  // let whatever was queued drain before reusing memory
+    // A failure part way leaves this batch's copies (and maybe kernels) queued
+    // on the slot's stream: wait for all of it before its arena and staging
+    // ranges go back to the allocators, or another batch could be given memory
+    // a copy is still writing into.
+    if (rc) (void)s->be->drain(free_slot);
     s->mu.lock();
     sl.launching = false;
     if (rc) {
@@ -608,12 +656,15 @@ ACE_API int ace_stream_create_host(ace_host_verify_fn fn, void *user, size_t are
     clear_error();
     if (!out || !fn) return fail(ACE_ERR_INVALID_ARG, "out or fn is NULL");
     *out = nullptr;
-    if (flags & ~(uint32_t)ACE_STREAM_PLAIN) return fail(ACE_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(uint32_t)(ACE_STREAM_PLAIN | ACE_STREAM_HOST_FAIL_LAUNCH))
+        return fail(ACE_ERR_INVALID_ARG, "unknown flags");
     if (max_inflight < 1 || max_inflight > 64) return fail(ACE_ERR_INVALID_ARG, "max_inflight must be 1..64");
     if (arena_bytes < 4096 || staging_bytes < 4096) return fail(ACE_ERR_INVALID_ARG, "arena or staging < 4096 bytes");
     ace_stream *s = new ace_stream;
-    s->be = std::make_unique<HostBackend>(fn, user, arena_bytes, fail_after);
-    int rc = stream_start(s, arena_bytes, staging_bytes, max_inflight, flags, false);
+    s->be = std::make_unique<HostBackend>(fn, user, arena_bytes, fail_after,
+                                          (flags & ACE_STREAM_HOST_FAIL_LAUNCH) != 0);
+    int rc = stream_start(s, arena_bytes, staging_bytes, max_inflight,
+                          flags & ~(uint32_t)ACE_STREAM_HOST_FAIL_LAUNCH, false);
     if (rc) {
         stream_free(s);
         return rc;
@@ -655,10 +706,12 @@ ACE_API int ace_verify_stream(ace_stream *s, const uint8_t *h_msg, const uint64_
 
     std::unique_lock<std::mutex> lock(s->mu);
     if (s->stop) return fail(ACE_ERR_INVALID_ARG, "stream is being destroyed");
+    InCall guard(s->cv_done, s->in_calls);  // released with the lock held (declared after it)
     size_t stage_off;
     while (!s->stage_alloc.alloc(lay.in_bytes, stage_off)) {
         if (flags & ACE_NONBLOCK) return fail(ACE_ERR_AGAIN, "staging full");
         s->cv_done.wait(lock);
+        if (s->stop) return fail(ACE_ERR_INVALID_ARG, "stream is being destroyed");
     }
     auto r = std::make_unique<Request>();
     r->ticket = s->next_ticket++;
@@ -681,6 +734,12 @@ ACE_API int ace_verify_stream(ace_stream *s, const uint8_t *h_msg, const uint64_
         off[0] = 0;
     }
     lock.lock();
+    if (s->stop) {
+        // destroy began during the copy: the server may already have drained
+        // the queue and left, so the request is not accepted
+        s->stage_alloc.release(stage_off, lay.in_bytes);
+        return fail(ACE_ERR_INVALID_ARG, "stream is being destroyed");
+    }
     *ticket_out = r->ticket;
     s->pending.push_back(r.get());
     s->reqs.emplace(r->ticket, std::move(r));
@@ -697,6 +756,7 @@ ACE_API int ace_stream_poll(ace_stream *s, uint64_t ticket, int wait)
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return fail(ACE_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
     Request *r = it->second.get();
+    InCall guard(s->cv_done, s->in_calls);
     if (wait)
         s->cv_done.wait(lock, [r] { return r->status != ACE_ERR_AGAIN; });
     if (r->status == ACE_ERR_AGAIN) return ACE_ERR_AGAIN;
@@ -748,11 +808,19 @@ ACE_API int ace_stream_destroy(ace_stream *s)
     clear_error();
     if (!s) return ACE_OK;
     {
-        std::lock_guard<std::mutex> lock(s->mu);
+        std::unique_lock<std::mutex> lock(s->mu);
         s->stop = true;
         s->cv_submit.notify_all();
+        // submitters waiting for staging give up; pollers wait for their
+        // requests, which the server still finishes
+        s->cv_done.notify_all();
     }
     if (s->server.joinable()) s->server.join();
+    {
+        // no client call may still be inside the engine when it is freed
+        std::unique_lock<std::mutex> lock(s->mu);
+        s->cv_done.wait(lock, [s] { return s->in_calls == 0; });
+    }
     stream_free(s);
     return ACE_OK;
 }
