@@ -78,6 +78,7 @@ class ace_profile(ctypes.Structure):
 
 
 _lib = None
+_DEFAULT_TUNING: Optional[dict] = None
 
 
 def load(path: str = LIB_PATH):
@@ -125,6 +126,8 @@ def load(path: str = LIB_PATH):
     lib.ace_profile_read.argtypes = [ctypes.POINTER(ace_profile), ctypes.c_int]
     lib.ace_profile_read.restype = ctypes.c_int
     _lib = lib
+    global _DEFAULT_TUNING
+    _DEFAULT_TUNING = get_tuning()  # nothing can have changed it before the first load
     return lib
 
 
@@ -391,6 +394,12 @@ def get_tuning() -> dict:
     t = ace_tuning()
     _check(load().ace_get_tuning(ctypes.byref(t)))
     return {k: getattr(t, k) for k, _ in ace_tuning._fields_}
+
+
+def default_tuning() -> dict:
+    """The library's own launch tuning (before any ace_set_tuning)."""
+    load()
+    return dict(_DEFAULT_TUNING)
 
 
 def set_tuning(**kw) -> dict:

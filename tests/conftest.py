@@ -25,3 +25,19 @@ def gpu_available() -> bool:
 def need_gpu():
     if not gpu_available():
         pytest.fail("GPU test run without a visible GPU")
+
+
+# Launch tunings the GPU parity tests run under: the library's own defaults and
+# the autotuned one saved for the device (the one the benchmarks install).
+# They reach different branches: persistent tiles per atomic grab, the
+# in-order graph's passes over its grid, the batch size from which an open
+# call bins by block count.
+TUNINGS = ["library-default", "saved"]
+
+
+def use_tuning(ace, which: str) -> dict:
+    from paper_2603_10242_amd import autotune
+    ace.set_tuning(**ace.default_tuning())
+    if which == "saved" and autotune.apply_saved() is None:
+        pytest.fail("no saved launch tuning for this device")
+    return ace.get_tuning()

@@ -1,7 +1,8 @@
 """Parity of the paper-form attestation check on the GPU (ace_verify_attestations)
 with the CPU oracle and the generator's truth mask: payload binding
 SHA-256(P) == obj_hash plus the credential HMAC(k, obj_hash || domain).
-Integer work: every bitmask word and count identical (tolerance 0)."""
+Integer work: every bitmask word and count identical (tolerance 0).  Every
+test runs under the library's default launch tuning and the saved autotuned one."""
 import sys
 
 import numpy as np
@@ -9,6 +10,8 @@ import pytest
 
 import oracle
 from paper_2603_10242_amd import workload as W
+
+from .conftest import TUNINGS, use_tuning
 
 pytestmark = pytest.mark.gpu
 
@@ -25,13 +28,15 @@ def note(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ace(need_gpu):
+@pytest.fixture(scope="module", params=TUNINGS)
+def ace(need_gpu, request):
     import torch
     from paper_2603_10242_amd import ace as A
     A.load()
     torch.cuda.set_device(0)
-    return A
+    note("launch tuning %s: %s" % (request.param, use_tuning(A, request.param)))
+    yield A
+    A.set_tuning(**A.default_tuning())
 
 
 def upload(ace, w, poff=None, ids=None, payload_dev=None):

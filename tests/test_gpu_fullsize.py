@@ -1,11 +1,14 @@
 """Parity at the benchmarks' full sizes, in the launch configuration bench.py
-times (binned, keys derived in the call, the saved launch tuning): every
-bitmask word, count and root against the CPU oracle, run multi-threaded over
-the whole workload (the C oracle verifies the 16M batch in a few seconds on
-the host's cores), and against the generator's truth mask.  Integer work:
-tolerance 0."""
+times (binned, keys derived in the call, the saved launch tuning) and in the
+other launch forms at those sizes (persistent verify, captured graphs of each
+form, the in-order kernel), under the saved tuning and the library's default
+one: every bitmask word, count and root against the CPU oracle, run
+multi-threaded over the whole workload (the C oracle verifies the 16M batch
+in a few seconds on the host's cores), and against the generator's truth
+mask.  Integer work: tolerance 0."""
 import os
 import sys
+from types import SimpleNamespace
 
 import numpy as np
 import pytest
@@ -13,9 +16,12 @@ import pytest
 import oracle
 from paper_2603_10242_amd import workload as W
 
+from .conftest import TUNINGS, use_tuning
+
 pytestmark = pytest.mark.gpu
 
 NT = max(1, min(16, os.cpu_count() or 1))  # oracle threads
+ORDERED, BUCKETED, PERSISTENT = 0x1, 0x2, 0x4
 
 
 def note(msg):
@@ -23,33 +29,143 @@ def note(msg):
     sys.stdout.flush()
 
 
+def popcount(words: np.ndarray) -> int:
+    return int(np.unpackbits(words.view(np.uint8)).sum())
+
+
 @pytest.fixture(scope="module")
 def ace(need_gpu):
     import torch
     from paper_2603_10242_amd import ace as A
-    from paper_2603_10242_amd import autotune
     A.load()
     torch.cuda.set_device(0)
-    autotune.apply_saved()
-    return A
+    use_tuning(A, "saved")
+    yield A
+    A.set_tuning(**A.default_tuning())
 
 
-def test_sweep_16M_keys_in_call(ace):
-    import torch
-    note("full size: 16M-tx sweep, 1M identities, binned, keys derived in the call")
+@pytest.fixture(scope="module")
+def sweep16(ace):
+    """The throughput sweep's 16M-transaction batch over 1M identities, resident,
+    with the oracle's result for all of it."""
+    note("generating the 16M-tx sweep workload")
     w = W.config3(n=16 << 20, n_id=1 << 20)
-    rev = ace.to_device(w.rev)
-    blk = ace.upload_block(w.msg, w.off, w.ids, w.tags)
-    ks = ace.rev_keyset(rev, w.salt, w.info)
-    ace.verify_batch(ks, [blk], flags=ace.ACE_BUCKETED)
-    torch.cuda.synchronize()
-    mask, count = blk.result()
     note("oracle on all %d transactions, %d threads" % (w.n, NT))
     keys = oracle.derive_keys(w.rev, w.salt, w.info, NT)
     omask, ocount = oracle.verify_batch(keys, w.msg, w.off, w.ids, w.tags, NT)
-    assert count == ocount == int(w.truth.sum()) and ocount < w.n
-    assert np.array_equal(mask, omask)
-    assert np.array_equal(mask, w.truth_bitmask())
+    assert ocount == int(w.truth.sum()) and ocount < w.n
+    assert np.array_equal(omask, w.truth_bitmask())
+    rev = ace.to_device(w.rev)
+    return SimpleNamespace(w=w, keys=keys, omask=omask, ocount=ocount, d_msg=ace.to_device(w.msg),
+                           mid=ace.midstate_keyset(rev, w.salt, w.info),
+                           rev=ace.rev_keyset(rev, w.salt, w.info))
+
+
+def sweep_block(ace, s, n):
+    w = s.w
+    return ace.upload_block(None, w.off[: n + 1], w.ids[:n], w.tags[:n], msg_dev=s.d_msg)
+
+
+def test_sweep_16M_keys_in_call(ace, sweep16):
+    import torch
+    note("full size: 16M-tx sweep, 1M identities, binned, keys derived in the call")
+    s = sweep16
+    blk = sweep_block(ace, s, s.w.n)
+    ace.verify_batch(s.rev, [blk], flags=BUCKETED)
+    torch.cuda.synchronize()
+    mask, count = blk.result()
+    assert count == s.ocount
+    assert np.array_equal(mask, s.omask)
+
+
+def expected_grab(ace, n: int) -> int:
+    """Wave tiles per atomic grab of the persistent verify kernel for a batch
+    of n transactions of the sweep (its bins pad to about n / 64 wave tiles):
+    nwaves / (4 grabs x 4 waves x workgroups), clamped to 1..8."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    wgs = ace.get_tuning()["verify_wgs_per_cu"] * cus
+    return max(1, min(8, (n // 64) // (wgs * 4 * 4)))
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_sweep_persistent_every_grab(ace, sweep16, tuning):
+    """The persistent verify kernel on prefixes of the 16M sweep that make it
+    take 1, 2, 3-4 and 8 wave tiles per atomic grab (library default: 8
+    workgroups per CU; saved: 2), with resident midstates and with keys
+    derived in the call; the open mode with auto_persistent set takes the
+    same kernel.  Every bitmask word against the oracle."""
+    import torch
+    s = sweep16
+    try:
+        use_tuning(ace, tuning)
+        grabs = set()
+        for n in (1 << 20, 2 << 20, 6 << 20, 16 << 20):
+            grabs.add(expected_grab(ace, n))
+            note("persistent, tuning %s, n=%d, grab %d" % (tuning, n, expected_grab(ace, n)))
+            blk = sweep_block(ace, s, n)
+            want = s.omask[: n // 32]
+            for kname, ks in (("midstate", s.mid), ("rev", s.rev)):
+                for flags, auto in ((BUCKETED | PERSISTENT, 0), (0, 1)):
+                    ace.set_tuning(auto_persistent=auto)
+                    blk.bitmask.fill_(-1)
+                    ace.verify_batch(ks, [blk], flags=flags)
+                    torch.cuda.synchronize()
+                    mask, count = blk.result()
+                    assert count == popcount(want), (n, kname, flags)
+                    assert np.array_equal(mask, want), (n, kname, flags)
+            ace.set_tuning(auto_persistent=0)
+            del blk
+        assert 8 in grabs and len(grabs) >= 3, grabs
+    finally:
+        use_tuning(ace, "saved")
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_sweep_16M_graph_forms(ace, sweep16, tuning):
+    """The 16M sweep split into three blocks, through graphs captured in each
+    form with keys derived in the replay: the in-order grid-stride kernel (8
+    to 32 passes over its grid), the binned dispatcher-scheduled kernel and
+    the persistent one (8 tiles per grab); two replays each, every word
+    against the oracle."""
+    import torch
+    s = sweep16
+    w = s.w
+    edges = [0, 5_000_000, 5_000_013, w.n]
+    want = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        if a % 32 == 0:
+            # a block that starts on a word boundary: a slice of the whole
+            # batch's result, bits past its end cleared
+            m = s.omask[a // 32: (b + 31) // 32].copy()
+            if b % 32:
+                m[-1] &= np.uint32((1 << (b % 32)) - 1)
+            want.append((m, popcount(m)))
+        else:
+            want.append(oracle.verify_batch(s.keys, w.msg, w.off[a:b + 1], w.ids[a:b],
+                                            w.tags[a:b], NT))
+    try:
+        use_tuning(ace, tuning)
+        for gflags in (ORDERED, BUCKETED, BUCKETED | PERSISTENT):
+            note("16M graph, tuning %s, flags %d" % (tuning, gflags))
+            g = ace.Graph(s.rev, max_blocks=4, max_tx=w.n, flags=gflags)
+            try:
+                for rep in range(2):
+                    blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b],
+                                               msg_dev=s.d_msg)
+                              for a, b in zip(edges[:-1], edges[1:])]
+                    for blk in blocks:
+                        blk.bitmask.fill_(-1)
+                    g.launch(blocks)
+                    torch.cuda.synchronize()
+                    for k, (blk, (omask, ocount)) in enumerate(zip(blocks, want)):
+                        mask, count = blk.result()
+                        assert count == ocount, (gflags, rep, k)
+                        assert np.array_equal(mask, omask), (gflags, rep, k)
+            finally:
+                g.close()
+    finally:
+        use_tuning(ace, "saved")
 
 
 def test_paper_form_16M_keys_in_call(ace):
@@ -70,17 +186,13 @@ def test_paper_form_16M_keys_in_call(ace):
     assert np.array_equal(mask, a.truth_bitmask())
 
 
-def test_batching_256_blocks_graph_replay(ace):
-    """The batching workload (256 blocks, 7.66M transactions, Zipf identities,
-    resident midstates) in one captured replay and in one eager multi-block
-    call: every block's bitmask and count against the oracle's for that
-    block."""
-    import torch
-    note("full size: batching workload, 256 blocks in one graph replay")
+@pytest.fixture(scope="module")
+def batching(ace):
+    """The batching workload (256 blocks of lognormal sizes, 7.66M transactions,
+    Zipf identities, resident midstates) with the oracle's result per block."""
+    note("generating the batching workload")
     w = W.config4()
     edges = np.concatenate([[0], np.cumsum(w.block_sizes)])
-    d_msg = ace.to_device(w.msg)
-    ks = ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info)
     note("oracle on all %d transactions, %d threads" % (w.n, NT))
     keys = oracle.derive_keys(w.rev, w.salt, w.info, NT)
     want = []
@@ -88,23 +200,47 @@ def test_batching_256_blocks_graph_replay(ace):
         off = w.off[a:b + 1] - w.off[a]
         want.append(oracle.verify_batch(keys, w.msg[int(w.off[a]):int(w.off[b])], off, w.ids[a:b],
                                         w.tags[a:b], NT))
-    g = ace.Graph(ks, max_blocks=len(edges) - 1, max_tx=w.n)
+    return SimpleNamespace(w=w, edges=edges, want=want, d_msg=ace.to_device(w.msg),
+                           ks=ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info))
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+@pytest.mark.parametrize("gflags", [0, BUCKETED | PERSISTENT, ORDERED])
+def test_batching_256_blocks_graph_replay(ace, batching, tuning, gflags):
+    """The batching workload in one captured replay (twice) and in one eager
+    multi-block call, with the graph captured in the open form (binned at this
+    size), as the persistent binned kernel (8 tiles per grab under the saved
+    tuning) and as the in-order grid-stride kernel (15 to 59 passes over its
+    grid): every block's bitmask and count against the oracle's for that
+    block."""
+    import torch
+    note("full size: batching workload, 256 blocks, graph flags %d, tuning %s" % (gflags, tuning))
+    bt = batching
+    w, edges = bt.w, bt.edges
     try:
-        for form in ("graph", "eager"):
-            blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
-                      for a, b in zip(edges[:-1], edges[1:])]
-            if form == "graph":
-                g.launch(blocks)
-            else:
-                ace.verify_batch(ks, blocks)
-            torch.cuda.synchronize()
-            for k, (blk, (omask, ocount)) in enumerate(zip(blocks, want)):
-                mask, count = blk.result()
-                a, b = int(edges[k]), int(edges[k + 1])
-                assert count == ocount == int(w.truth[a:b].sum()), (form, k)
-                assert np.array_equal(mask, omask), (form, k)
+        use_tuning(ace, tuning)
+        g = ace.Graph(bt.ks, max_blocks=len(edges) - 1, max_tx=w.n, flags=gflags)
+        try:
+            for form in ("graph", "graph", "eager"):
+                blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b],
+                                           msg_dev=bt.d_msg)
+                          for a, b in zip(edges[:-1], edges[1:])]
+                for blk in blocks:
+                    blk.bitmask.fill_(-1)
+                if form == "graph":
+                    g.launch(blocks)
+                else:
+                    ace.verify_batch(bt.ks, blocks, flags=gflags)
+                torch.cuda.synchronize()
+                for k, (blk, (omask, ocount)) in enumerate(zip(blocks, bt.want)):
+                    mask, count = blk.result()
+                    a, b = int(edges[k]), int(edges[k + 1])
+                    assert count == ocount == int(w.truth[a:b].sum()), (form, k)
+                    assert np.array_equal(mask, omask), (form, k)
+        finally:
+            g.close()
     finally:
-        g.close()
+        use_tuning(ace, "saved")
 
 
 def test_serving_full_size_requests(ace):

@@ -1,12 +1,17 @@
 """Captured batches (ace_graph_*): one capture replayed for different block
 mixes must give exactly what the eager call gives and what the generator's
-truth mask says, replay after replay, with eager work in between."""
+truth mask and the CPU oracle say, replay after replay, with eager work in
+between, under the library's default launch tuning and the saved autotuned
+one."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2603_10242_amd import workload as W
+
+from .conftest import TUNINGS, use_tuning
 
 pytestmark = pytest.mark.gpu
 
@@ -16,18 +21,25 @@ def note(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ace(need_gpu):
+@pytest.fixture(scope="module", params=TUNINGS)
+def ace(need_gpu, request):
     import torch
     from paper_2603_10242_amd import ace as A
     A.load()
     torch.cuda.set_device(0)
-    return A
+    note("launch tuning %s: %s" % (request.param, use_tuning(A, request.param)))
+    yield A
+    A.set_tuning(**A.default_tuning())
 
 
 @pytest.fixture(scope="module")
 def data():
     return W.subset(W.config2(), 0, 80_000)
+
+
+@pytest.fixture(scope="module")
+def okeys(data):
+    return oracle.derive_keys(data.rev, data.salt, data.info, 8)
 
 
 def cut(ace, w, edges, d_msg):
@@ -51,16 +63,20 @@ def mixes(n):
     return out
 
 
-def check(blocks, edges, truth):
+def check(blocks, edges, w, keys):
+    """Every block's bitmask and count against the oracle's for its range and
+    against the generator's truth mask."""
     for blk, a, b in zip(blocks, edges[:-1], edges[1:]):
         mask, count = blk.result()
-        assert count == int(truth[a:b].sum()), (a, b)
-        assert np.array_equal(mask, W.pack_bits(truth[a:b])), (a, b)
+        omask, ocount = oracle.verify_batch(keys, w.msg, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], 8)
+        assert count == ocount == int(w.truth[a:b].sum()), (a, b)
+        assert np.array_equal(mask, omask), (a, b)
+        assert np.array_equal(mask, W.pack_bits(w.truth[a:b])), (a, b)
 
 
 @pytest.mark.parametrize("keys", ["midstate", "rev"])
-@pytest.mark.parametrize("flags", [0, 0x1])
-def test_graph_replays_match_eager(ace, data, keys, flags):
+@pytest.mark.parametrize("flags", [0, 0x1, 0x2 | 0x4])
+def test_graph_replays_match_eager(ace, data, okeys, keys, flags):
     import torch
     note("graph keys=%s flags=%d" % (keys, flags))
     w = data
@@ -75,7 +91,7 @@ def test_graph_replays_match_eager(ace, data, keys, flags):
             blocks = cut(ace, w, edges, d_msg)
             g.launch(blocks)
             torch.cuda.synchronize()
-            check(blocks, edges, w.truth)
+            check(blocks, edges, w, okeys)
             # eager pass over the same blocks, plus unrelated torch work
             eager = cut(ace, w, edges, d_msg)
             ace.verify_batch(ks, eager, flags=flags)
@@ -90,13 +106,15 @@ def test_graph_replays_match_eager(ace, data, keys, flags):
         g.close()
 
 
-def test_graph_back_to_back_replays(ace, data):
+@pytest.mark.parametrize("flags", [0, 0x1, 0x2 | 0x4])
+def test_graph_back_to_back_replays(ace, data, okeys, flags):
     """Replays queued without a host sync in between (both pinned block lists in use)."""
     import torch
+    note("graph back to back flags=%d" % flags)
     w = data
     ks = ace.midstate_keyset(ace.to_device(w.rev), w.salt, w.info)
     d_msg = ace.to_device(w.msg)
-    g = ace.Graph(ks, max_blocks=300, max_tx=w.n)
+    g = ace.Graph(ks, max_blocks=300, max_tx=w.n, flags=flags)
     try:
         plan = mixes(w.n)
         sets = [cut(ace, w, e, d_msg) for e in plan]
@@ -104,7 +122,7 @@ def test_graph_back_to_back_replays(ace, data):
             g.launch(blocks)
         torch.cuda.synchronize()
         for blocks, edges in zip(sets, plan):
-            check(blocks, edges, w.truth)
+            check(blocks, edges, w, okeys)
     finally:
         g.close()
 

@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle and with the
 generator's truth mask.  Integer work: every bitmask word and count must be
-identical (tolerance 0)."""
+identical (tolerance 0).  Every test runs under the library's default launch
+tuning and under the saved autotuned one."""
 import sys
 
 import numpy as np
@@ -8,6 +9,8 @@ import pytest
 
 import oracle
 from paper_2603_10242_amd import workload as W
+
+from .conftest import TUNINGS, use_tuning
 
 pytestmark = pytest.mark.gpu
 
@@ -23,13 +26,23 @@ def note(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ace(need_gpu):
+@pytest.fixture(scope="module", params=TUNINGS)
+def ace(need_gpu, request):
     import torch
     from paper_2603_10242_amd import ace as A
     A.load()
     torch.cuda.set_device(0)
-    return A
+    note("launch tuning %s: %s" % (request.param, use_tuning(A, request.param)))
+    yield A
+    A.set_tuning(**A.default_tuning())
+
+
+@pytest.fixture(scope="module")
+def block_scale():
+    """The block-scale workload with the oracle's keys and whole-batch result."""
+    w = W.config2()
+    keys = oracle.derive_keys(w.rev, w.salt, w.info, 8)
+    return w, keys, oracle.verify_batch(keys, w.msg, w.off, w.ids, w.tags, 8)
 
 
 def oracle_result(w, keys=None, nthreads=8, ids=None, off=None):
@@ -270,16 +283,18 @@ def test_long_messages_catch_all_bin(ace):
 
 # ------------------------------------------------------------------ batch shapes, edge cases
 @pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 63, 64, 65, 4097])
-def test_batch_sizes(ace, n):
+def test_batch_sizes(ace, block_scale, n):
     note("batch size n=%d" % n)
-    base = W.config2()
+    base, keys, _ = block_scale
     w = W.subset(base, 0, n)
+    omask, ocount = oracle_result(w, keys=keys)
     ks = keysets(ace, w)
-    for mode in MODES.values():
+    for mode in [0] + list(MODES.values()):
         for name in ("midstate", "rev"):
             mask, count = run(ace, w, ks[name], mode)
-            assert count == int(w.truth.sum())
+            assert count == ocount == int(w.truth.sum())
             assert mask.shape[0] == (n + 31) // 32
+            assert np.array_equal(mask, omask)
             assert np.array_equal(mask, w.truth_bitmask())
 
 
@@ -404,10 +419,10 @@ def test_empty_registry(ace):
 
 # ------------------------------------------------------------------ several blocks in one call
 @pytest.mark.parametrize("mode", list(MODES))
-def test_multi_block(ace, mode):
+def test_multi_block(ace, block_scale, mode):
     import torch
     note("multi-block mode=%s" % mode)
-    w = W.config2()
+    w, keys, _ = block_scale
     sizes = [0, 1, 100, 3000, 64, 65, 5000, 0, 2048, 31, 20000, 7]
     ks = keysets(ace, w)["rev"]
     d_msg = ace.to_device(w.msg)
@@ -425,26 +440,33 @@ def test_multi_block(ace, mode):
     for blk, (lo, hi) in zip(blocks, parts):
         mask, count = blk.result()
         truth = w.truth[lo:hi]
-        assert count == int(truth.sum()), (lo, hi)
+        omask, ocount = oracle.verify_batch(keys, w.msg, w.off[lo:hi + 1], w.ids[lo:hi],
+                                            w.tags[lo:hi], 8)
+        assert count == ocount == int(truth.sum()), (lo, hi)
+        assert np.array_equal(mask, omask), (lo, hi)
         assert np.array_equal(mask, W.pack_bits(truth)), (lo, hi)
 
 
-def test_many_blocks_256(ace):
+def test_many_blocks_256(ace, block_scale):
     import torch
     note("256 blocks")
-    w = W.subset(W.config2(), 0, 60_000)
+    base, keys, _ = block_scale
+    w = W.subset(base, 0, 60_000)
     r = np.random.Generator(np.random.PCG64(256))
     cuts = np.sort(r.choice(np.arange(1, w.n), size=255, replace=False))
     edges = np.concatenate([[0], cuts, [w.n]])
     d_msg = ace.to_device(w.msg)
     blocks = [ace.upload_block(None, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], msg_dev=d_msg)
               for a, b in zip(edges[:-1], edges[1:])]
-    for mode in MODES.values():
+    want = [oracle.verify_batch(keys, w.msg, w.off[a:b + 1], w.ids[a:b], w.tags[a:b], 8)
+            for a, b in zip(edges[:-1], edges[1:])]
+    for mode in [0] + list(MODES.values()):
         ace.verify_batch(keysets(ace, w)["midstate"], blocks, flags=mode)
         torch.cuda.synchronize()
-        for blk, a, b in zip(blocks, edges[:-1], edges[1:]):
+        for blk, a, b, (omask, ocount) in zip(blocks, edges[:-1], edges[1:], want):
             mask, count = blk.result()
-            assert count == int(w.truth[a:b].sum())
+            assert count == ocount == int(w.truth[a:b].sum())
+            assert np.array_equal(mask, omask)
             assert np.array_equal(mask, W.pack_bits(w.truth[a:b]))
 
 
