@@ -23,7 +23,8 @@
  *   - d_* arguments are HIP device pointers owned by the caller; h_* are host
  *     pointers read before the call returns.  The library never frees or
  *     retains caller memory and allocates no device memory: scratch space is
- *     the caller's workspace.
+ *     the caller's workspace (ace_verify_batch_noalloc: a static array the
+ *     library holds on each GPU).
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
  *     asynchronously on it; outputs are valid once the stream has reached
  *     the end of the call's work.
@@ -194,6 +195,33 @@ ACE_API int ace_verify_batch(const ace_keyset *keys, const ace_block *blocks, ui
 ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blocks,
                                     uint32_t n_blocks, void *d_workspace, size_t ws_bytes,
                                     uint32_t flags, void *stream);
+
+/*
+ * ace_verify_batch_noalloc -- ace_verify_batch for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same operation,
+ * arguments (less the workspace), flags, results, errors and stream
+ * semantics as ace_verify_batch; the call allocates nothing (no hipMalloc,
+ * no stream or event) and uses instead a scratch array of
+ * ACE_SCRATCH_BYTES that the library holds in each GPU's memory until the
+ * process ends.
+ *   - A call whose workspace (ace_verify_workspace_size with the same
+ *     arguments) exceeds ACE_SCRATCH_BYTES returns ACE_ERR_TOO_LARGE before
+ *     anything is enqueued.  A binned call needs about 28 bytes per
+ *     transaction (64 MiB: about 2.3M transactions with cached midstates);
+ *     keys derived in the call add 64 bytes per identity; an ordered call
+ *     needs only the block table and those midstates.
+ *   - Every call on one GPU uses that GPU's one array: calls that overlap on
+ *     one GPU (on different streams, or from different threads, without
+ *     ordering between them) race and give undefined results.  Calls ordered
+ *     on one stream are safe; each clears what it needs.
+ *   - With keys derived in a binned call, the derivation runs on `stream`
+ *     before the binning passes (ace_verify_batch may run it beside them on
+ *     a second stream).  Stage timing (ace_profile_enable) does not cover it.
+ */
+#define ACE_SCRATCH_BYTES (64u << 20)
+ACE_API int ace_verify_batch_noalloc(const ace_keyset *keys, const ace_block *blocks,
+                                     uint32_t n_blocks, uint32_t flags, void *stream);
 
 /*
  * Tuning of the launch shapes (process-wide).  The autotuner measures the

@@ -34,6 +34,8 @@ ACE_PER_TX_KEYS = 0x8
 ACE_KEYS_MIDSTATE = 0
 ACE_KEYS_REV = 1
 
+ACE_SCRATCH_BYTES = 64 << 20  # scratch array of ace_verify_batch_noalloc, per device
+
 
 class AceError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -112,6 +114,9 @@ def load(path: str = LIB_PATH):
     lib.ace_valu_rate.argtypes = [u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.ace_valu_rate.restype = ctypes.c_int
     lib.ace_verify_attestations.argtypes = lib.ace_verify_batch.argtypes
+    lib.ace_verify_batch_noalloc.argtypes = [ctypes.POINTER(ace_keyset), ctypes.POINTER(ace_block),
+                                             u32, u32, vp]
+    lib.ace_verify_batch_noalloc.restype = ctypes.c_int
     lib.ace_verify_attestations.restype = ctypes.c_int
     lib.ace_get_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
     lib.ace_set_tuning.argtypes = [ctypes.POINTER(ace_tuning)]
@@ -320,6 +325,16 @@ def verify_attestations(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock],
                         stream=None) -> torch.Tensor:
     """ace_verify_attestations (blocks uploaded with record_bytes=72)."""
     return _verify(load().ace_verify_attestations, keyset, blocks, ws, flags, stream, 72)
+
+
+def verify_batch_noalloc(keyset: DeviceKeyset, blocks: Sequence[DeviceBlock], flags: int = 0,
+                         stream=None) -> None:
+    """ace_verify_batch_noalloc: the library's static scratch array instead of
+    a workspace (at most ACE_SCRATCH_BYTES; larger calls raise)."""
+    ks, keep = keyset.struct()
+    arr = _blocks_array(blocks)
+    _check(load().ace_verify_batch_noalloc(ctypes.byref(ks), arr, len(blocks), flags,
+                                           _stream(stream)))
 
 
 def merkle_roots(trees: Sequence[tuple[torch.Tensor, torch.Tensor, int, torch.Tensor]],

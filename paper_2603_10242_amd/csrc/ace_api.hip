@@ -397,8 +397,11 @@ void launch_binned(const Plan &p, unsigned g, hipStream_t s, const Batch &bt, co
 
 // The launch sequence after the block table is in place.  `graph` marks a
 // capture: sizes then come from the device header and every grid is fixed.
+// `fork`: a binned call with keys derived in it may run the derivation on
+// the thread's second stream (created on first use); without it the
+// derivation runs first on `s`.
 int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const HkdfParams &hp,
-                   uint8_t *ws, hipStream_t s, ProfCall *prof, bool graph)
+                   uint8_t *ws, hipStream_t s, ProfCall *prof, bool graph, bool fork = true)
 {
     int rc;
     const ace_tuning tn = tuning();
@@ -423,7 +426,7 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
         if (keys->n_id) {
             unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
             hipStream_t ds = s;
-            if (binned && (graph || p.total_tx) && (fk = fork_ctx())) {
+            if (fork && binned && (graph || p.total_tx) && (fk = fork_ctx())) {
                 if ((rc = check_hip(hipEventRecord(fk->fork, s), "hipEventRecord"))) return rc;
                 if ((rc = check_hip(hipStreamWaitEvent(fk->aux, fk->fork, 0), "hipStreamWaitEvent")))
                     return rc;
@@ -814,26 +817,15 @@ ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block
 
 namespace {
 
-int verify_impl(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
-                void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream, bool attest)
+// The block table and the launch sequence of a checked call, with `ws` as its
+// workspace.  `noalloc`: no stage events, no second stream (both are created
+// on first use).
+int run_plan(const Plan &p, const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+             const HkdfParams &hp, uint8_t *ws, void *stream, bool noalloc)
 {
-    clear_error();
-    Plan p;
-    int rc = make_plan(keys, blocks, n_blocks, flags, p, attest);
-    if (rc) return rc;
-    if (n_blocks == 0) return ACE_OK;
-    if (!d_workspace) return fail(ACE_ERR_INVALID_ARG, "d_workspace is NULL");
-    if (!aligned(d_workspace, 256)) return fail(ACE_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
-    if (ws_bytes < p.bytes)
-        return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
-    HkdfParams hp;
-    memset(&hp, 0, sizeof hp);
-    if (p.rev && (rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len)))
-        return rc;
-
+    int rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    ProfCall *prof = prof_begin(s);
-    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    ProfCall *prof = noalloc ? nullptr : prof_begin(s);
     DevBlock *table = reinterpret_cast<DevBlock *>(ws + p.off_descs);
 
     Batch bt;
@@ -866,7 +858,62 @@ int verify_impl(const ace_keyset *keys, const ace_block *blocks, uint32_t n_bloc
         }
     }
     bt.table = n_blocks > 1 ? table : nullptr;
-    return enqueue_stages(p, bt, keys, hp, ws, s, prof, false);
+    return enqueue_stages(p, bt, keys, hp, ws, s, prof, false, !noalloc);
+}
+
+int verify_impl(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks,
+                void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream, bool attest)
+{
+    clear_error();
+    Plan p;
+    int rc = make_plan(keys, blocks, n_blocks, flags, p, attest);
+    if (rc) return rc;
+    if (n_blocks == 0) return ACE_OK;
+    if (!d_workspace) return fail(ACE_ERR_INVALID_ARG, "d_workspace is NULL");
+    if (!aligned(d_workspace, 256)) return fail(ACE_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
+    if (ws_bytes < p.bytes)
+        return fail(ACE_ERR_NO_MEMORY, "workspace %zu bytes, need %zu", ws_bytes, p.bytes);
+    HkdfParams hp;
+    memset(&hp, 0, sizeof hp);
+    if (p.rev && (rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len)))
+        return rc;
+    return run_plan(p, keys, blocks, n_blocks, hp, static_cast<uint8_t *>(d_workspace), stream,
+                    false);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Scratch memory of ace_verify_batch_noalloc: a static device array that every
+// GPU the library runs on holds until the process ends.  Its name in host code
+// is only a stand-in for the symbol; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+// ------------------------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[ACE_SCRATCH_BYTES];
+
+namespace {
+
+// This device's address of `scratch`, looked up once per device (with that
+// device current) on the first no-allocation call there.
+int scratch_base(uint8_t **out)
+{
+    static std::mutex mu;
+    static std::vector<uint8_t *> base;
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)base.size() <= dev) base.resize(dev + 1, nullptr);
+    if (!base[dev]) {
+        void *ptr = nullptr;
+        if ((rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress")))
+            return rc;
+        if (!ptr || !aligned(ptr, 256))
+            return fail(ACE_ERR_DEVICE, "scratch array at %p is not 256-byte aligned", ptr);
+        base[dev] = static_cast<uint8_t *>(ptr);
+    }
+    *out = base[dev];
+    return ACE_OK;
 }
 
 }  // namespace
@@ -884,6 +931,28 @@ ACE_API int ace_verify_attestations(const ace_keyset *keys, const ace_block *blo
                                     uint32_t flags, void *stream)
 {
     return verify_impl(keys, blocks, n_blocks, d_workspace, ws_bytes, flags, stream, true);
+}
+
+ACE_API int ace_verify_batch_noalloc(const ace_keyset *keys, const ace_block *blocks,
+                                     uint32_t n_blocks, uint32_t flags, void *stream)
+{
+    clear_error();
+    Plan p;
+    int rc = make_plan(keys, blocks, n_blocks, flags, p, false);
+    if (rc) return rc;
+    if (n_blocks == 0) return ACE_OK;
+    if (p.bytes > (size_t)ACE_SCRATCH_BYTES)
+        return fail(ACE_ERR_TOO_LARGE,
+                    "the call needs %zu bytes of scratch, the library holds %zu per device "
+                    "(ace_verify_batch takes a workspace of any size)",
+                    p.bytes, (size_t)ACE_SCRATCH_BYTES);
+    HkdfParams hp;
+    memset(&hp, 0, sizeof hp);
+    if (p.rev && (rc = fill_hkdf(hp, keys->h_salt, keys->salt_len, keys->h_info, keys->info_len)))
+        return rc;
+    uint8_t *ws = nullptr;
+    if ((rc = scratch_base(&ws))) return rc;
+    return run_plan(p, keys, blocks, n_blocks, hp, ws, stream, true);
 }
 
 ACE_API int ace_profile_enable(int on)

@@ -108,6 +108,36 @@ def test_argument_errors_are_reported_before_any_launch(lib):
                                 None) == ace.ACE_ERR_INVALID_ARG
 
 
+def test_noalloc_refuses_calls_beyond_its_scratch_array(lib):
+    """ace_verify_batch_noalloc checks its arguments like ace_verify_batch and
+    refuses a call whose workspace exceeds the static scratch array, before
+    touching the GPU; the binding's constant is the header's."""
+    from paper_2603_10242_amd import ace
+    text = open(HEADER).read()
+    m = re.search(r"#define ACE_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == ace.ACE_SCRATCH_BYTES
+    ks, keep = _keyset(ace)
+    blk = (ace.ace_block * 1)(_block(ace, n=3_000_000))
+    assert lib.ace_verify_workspace_size(ctypes.byref(ks), blk, 1, ace.ACE_BUCKETED) > \
+        ace.ACE_SCRATCH_BYTES
+    assert lib.ace_verify_batch_noalloc(ctypes.byref(ks), blk, 1, ace.ACE_BUCKETED,
+                                        None) == ace.ACE_ERR_TOO_LARGE
+    assert b"scratch" in lib.ace_last_error()
+    # keys derived in the call: 64 bytes per identity on top
+    ks2, k2 = _keyset(ace, kind=1, rev=0x7000, n_id=1 << 20)
+    small = (ace.ace_block * 1)(_block(ace, n=1000))
+    assert lib.ace_verify_batch_noalloc(ctypes.byref(ks2), small, 1, ace.ACE_ORDERED,
+                                        None) == ace.ACE_ERR_TOO_LARGE
+    # the same argument errors as the workspace form
+    assert lib.ace_verify_batch_noalloc(ctypes.byref(ks), small, 1, ace.ACE_ORDERED | ace.ACE_BUCKETED,
+                                        None) == ace.ACE_ERR_INVALID_ARG
+    bad = (ace.ace_block * 1)(_block(ace, n=1000, d_tag=0))
+    assert lib.ace_verify_batch_noalloc(ctypes.byref(ks), bad, 1, 0, None) == ace.ACE_ERR_INVALID_ARG
+    assert lib.ace_verify_batch_noalloc(None, small, 1, 0, None) == ace.ACE_ERR_INVALID_ARG
+    # nothing to do
+    assert lib.ace_verify_batch_noalloc(ctypes.byref(ks), small, 0, 0, None) == ace.ACE_OK
+
+
 def test_derive_argument_errors(lib):
     from paper_2603_10242_amd import ace
     salt = ctypes.create_string_buffer(b"s" * 32)
