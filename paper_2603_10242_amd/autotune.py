@@ -63,6 +63,17 @@ def apply_saved(verbose: bool = False) -> dict | None:
     return saved["tuning"]
 
 
+def saved_graph_flags() -> int:
+    """Launch form of the batching graph in the saved tuning (0: the open form,
+    binned at the batching workload's size)."""
+    try:
+        arch, cus = device_key()
+        with open(tuning_path(arch, cus)) as fh:
+            return int(json.load(fh).get("graph_flags", 0))
+    except Exception:
+        return 0
+
+
 def _time(fn, reps: int = 5) -> float:
     import torch
     fn()
