@@ -155,8 +155,10 @@ struct Plan {
     uint64_t total_tiles;
     uint64_t total_waves;
     uint64_t max_pos;  // upper bound of bin-order positions
+    uint64_t tstride;  // tiles the per-tile bin counts have room for (row length)
     // workspace layout (byte offsets)
-    size_t off_ctrl, off_hdr, off_descs, off_mid, off_perm, off_rec, off_posof, off_vperm, bytes;
+    size_t off_ctrl, off_hdr, off_descs, off_mid, off_thist, off_perm, off_rec, off_posof,
+        off_vperm, bytes;
 };
 
 int check_keyset(const ace_keyset *keys, uint32_t flags, Plan &p)
@@ -218,9 +220,10 @@ int check_blocks(const ace_block *blocks, uint32_t n_blocks, uint64_t &total, ui
 }
 
 // Mode, persistence and workspace layout for n_blocks blocks of `total`
-// transactions in all (exact sizes for a call, maxima for a graph).
-void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t flags, bool graph,
-            Plan &p)
+// transactions in all (exact sizes for a call, maxima for a graph).  `tiles`:
+// the call's tiles of kTile transactions (a graph bounds them from the maxima).
+void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint64_t tiles,
+            uint32_t flags, bool graph, Plan &p)
 {
     const ace_tuning t = tuning();
     p.n_blocks = n_blocks;
@@ -231,12 +234,15 @@ void layout(const ace_keyset *keys, uint32_t n_blocks, uint64_t total, uint32_t 
     p.persistent = binned && ((flags & ACE_PERSISTENT) ||
                               (!(flags & (ACE_ORDERED | ACE_BUCKETED)) && t.auto_persistent));
     p.max_pos = total + 64ull * kBins;
+    p.tstride = graph ? (total + kTile - 1) / kTile + n_blocks : tiles;
+    if (p.tstride < 1) p.tstride = 1;
     const bool table = graph || n_blocks > 1;
     size_t o = 0;
     p.off_ctrl = o;  o = align_up(o + sizeof(Ctrl), 256);
     p.off_hdr = o;   o = align_up(o + (graph ? sizeof(BatchHdr) : 0), 256);
     p.off_descs = o; o = align_up(o + (table ? (size_t)n_blocks * sizeof(DevBlock) : 0), 256);
     p.off_mid = o;   o = align_up(o + (p.rev && !p.per_tx ? 64ull * keys->n_id : 0), 256);
+    p.off_thist = o; o = align_up(o + (binned ? 4ull * kBins * p.tstride : 0), 256);
     p.off_perm = o;  o = align_up(o + (binned ? 8ull * p.max_pos : 0), 256);
     p.off_rec = o;   o = align_up(o + (binned ? sizeof(TxRec) * p.max_pos : 0), 256);
     p.off_posof = o; o = align_up(o + (binned ? 4ull * total : 0), 256);
@@ -255,7 +261,7 @@ int make_plan(const ace_keyset *keys, const ace_block *blocks, uint32_t n_blocks
     p.total_tx = total;
     p.total_tiles = tiles;
     p.total_waves = waves;
-    layout(keys, n_blocks, total, flags, false, p);
+    layout(keys, n_blocks, total, tiles, flags, false, p);
     return ACE_OK;
 }
 
@@ -486,11 +492,13 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     const uint64_t tiles_bound = graph ? (p.total_tx + kTile - 1) / kTile + p.n_blocks : p.total_tiles;
     const unsigned gtiles = grid_for(tiles_bound, 1, tn.aux_wgs_per_cu * cus);
 
-    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id);
+    uint32_t *thist = reinterpret_cast<uint32_t *>(ws + p.off_thist);
+    hipLaunchKernelGGL(k_bin_count, dim3(gtiles), dim3(kWG), 0, s, bt, thist, p.tstride, keys->n_id);
     if ((rc = launch_status("k_bin_count launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBins), 0, s, ctrl);
+    hipLaunchKernelGGL(k_bin_scan, dim3(kBins), dim3(kScanWG), 0, s, bt, ctrl, thist, p.tstride);
     if ((rc = launch_status("k_bin_scan launch"))) return rc;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, keys->n_id, perm, rec,
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gtiles), dim3(kWG), 0, s, bt, ctrl, thist, p.tstride,
+                       keys->n_id, perm, rec,
                        pos_of, tn.wide_min_len);
     if ((rc = launch_status("k_bin_scatter launch"))) return rc;
     if (fk && (rc = check_hip(hipStreamWaitEvent(s, fk->join, 0), "hipStreamWaitEvent"))) return rc;
@@ -993,7 +1001,7 @@ ACE_API size_t ace_graph_workspace_size(const ace_keyset *keys, uint32_t max_blo
     Plan p;
     if (check_keyset(keys, flags, p) != ACE_OK) return 0;
     if (max_blocks == 0 || max_blocks >= (1u << 24) || max_tx > ACE_MAX_TX) return 0;
-    layout(keys, max_blocks, max_tx, flags, true, p);
+    layout(keys, max_blocks, max_tx, 0, flags, true, p);
     return p.bytes;
 }
 
@@ -1009,7 +1017,7 @@ ACE_API int ace_graph_create(const ace_keyset *keys, uint32_t max_blocks, uint64
     if (max_blocks == 0) return fail(ACE_ERR_INVALID_ARG, "max_blocks is 0");
     if (max_blocks >= (1u << 24)) return fail(ACE_ERR_RANGE, "max_blocks >= 2^24");
     if (max_tx > ACE_MAX_TX) return fail(ACE_ERR_RANGE, "max_tx exceeds ACE_MAX_TX");
-    layout(keys, max_blocks, max_tx, flags, true, p);
+    layout(keys, max_blocks, max_tx, 0, flags, true, p);
     p.total_tx = max_tx;
     p.total_tiles = 0;
     p.total_waves = 0;

@@ -52,20 +52,15 @@ struct Batch {
     uint64_t total_waves;
 };
 
-// Control words of a bucketed pass (start of the workspace).
-// Copies of the per-bin counters: workgroup w of the count and scatter passes
-// uses copy w % kCopies, so a counter sees a few hundred atomics instead of
-// one per workgroup (same-address atomics serialize).
-constexpr uint32_t kCopies = 32;
-
+// Control words of a bucketed pass (start of the workspace).  The per-tile
+// bin counts live beside them in the workspace (see k_bin_count).
 struct Ctrl {
-    uint32_t hist[kBins * kCopies];    // transactions per (bin, copy)
-    uint32_t cursor[kBins * kCopies];  // next free position per (bin, copy) (scatter)
-    uint32_t ostart[kBins];  // bins in order o = 63 - bin (longest first): padded start
-    uint32_t ocount[kBins];  // real transactions
-    uint32_t opad[kBins];    // count rounded up to a multiple of 64
-    uint32_t total_pos;      // sum of opad
-    uint32_t work;           // wave-tile counter of the persistent verify
+    uint32_t bincount[kBins];  // transactions per bin (k_bin_scan)
+    uint32_t ostart[kBins];    // bins in order o = 63 - bin (longest first): padded start
+    uint32_t ocount[kBins];    // real transactions
+    uint32_t opad[kBins];      // count rounded up to a multiple of 64
+    uint32_t total_pos;        // sum of opad
+    uint32_t work;             // wave-tile counter of the persistent verify
     uint32_t pad_[62];
 };
 

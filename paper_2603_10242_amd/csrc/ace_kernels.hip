@@ -410,19 +410,21 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? 6 :
 }
 
 // ------------------------------------------------------------------------------------------
-// Binning by inner block count.
+// Binning by inner block count.  Three passes over the batch's tiles of kTile
+// transactions: k_bin_count writes each tile's bin histogram into the table
+// thist[bin][tile]; k_bin_scan turns every bin's row into exclusive prefixes
+// over the tiles and stores the bin totals; k_bin_scatter then knows where each
+// tile's transactions of each bin go without any global atomic: bins laid out
+// longest first, each padded to a multiple of 64, tiles in order within a bin.
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
 {
     const Totals T = totals(bt);
     const uint32_t t = blockIdx.x * kWG + threadIdx.x;
     for (uint32_t b = t; b < T.n_blocks; b += gridDim.x * kWG) *get_block(bt, T, b).count = 0;
-    if (ctrl && blockIdx.x == 0) {
-        for (uint32_t k = threadIdx.x; k < kBins * kCopies; k += kWG) {
-            ctrl->hist[k] = 0;
-            ctrl->cursor[k] = 0;
-        }
-        if (threadIdx.x == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
+    if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->total_pos = 0;
+        ctrl->work = 0;
     }
 }
 
@@ -433,14 +435,15 @@ __device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i, uin
     return (a <= e && d.id[i] < n_id) ? e - a : 0;
 }
 
-__global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl, uint32_t n_id)
+__global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, uint32_t *__restrict__ thist,
+                                                   uint64_t tstride, uint32_t n_id)
 {
     constexpr int kPer = kTile / kWG;
     __shared__ uint32_t h[kBins];
-    if (threadIdx.x < kBins) h[threadIdx.x] = 0;
-    __syncthreads();
     const Totals T = totals(bt);
     for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+        if (threadIdx.x < kBins) h[threadIdx.x] = 0;
+        __syncthreads();
         const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
         const uint64_t i0 = (tile - d.tile0) * kTile;
         uint32_t bins[kPer];
@@ -452,39 +455,50 @@ __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, Ctrl *ctrl, uint32_
 #pragma unroll
         for (int k = 0; k < kPer; ++k)
             if (bins[k] < kBins) atomicAdd(&h[bins[k]], 1u);
+        __syncthreads();
+        if (threadIdx.x < kBins) thist[threadIdx.x * tstride + tile] = h[threadIdx.x];
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < kBins && h[threadIdx.x])
-        atomicAdd(&ctrl->hist[threadIdx.x * kCopies + blockIdx.x % kCopies], h[threadIdx.x]);
 }
 
-// One wave: bins laid out longest first so the longest waves start first;
-// within a bin, copy c of its counters starts after copies 0 .. c-1.
-__global__ void k_bin_scan(Ctrl *ctrl)
+// One workgroup per bin: the bin's per-tile counts become exclusive prefixes
+// (in place), and the bin's total goes to ctrl->bincount.
+constexpr int kScanWG = 1024;
+__global__ void __launch_bounds__(kScanWG) k_bin_scan(Batch bt, Ctrl *ctrl,
+                                                      uint32_t *__restrict__ thist, uint64_t tstride)
 {
-    const uint32_t o = threadIdx.x;          // order position
-    const uint32_t bin = kBins - 1 - o;
-    uint32_t cnt = 0;
-    for (uint32_t c = 0; c < kCopies; ++c) cnt += ctrl->hist[bin * kCopies + c];
-    const uint32_t pad = (cnt + 63u) & ~63u;
-    __shared__ uint32_t s[kBins];
-    s[o] = pad;
+    __shared__ uint32_t part[kScanWG];
+    const uint32_t bin = blockIdx.x;
+    const uint32_t t = threadIdx.x;
+    const Totals T = totals(bt);
+    uint32_t *row = thist + bin * tstride;
+    // thread t owns a contiguous run of tiles
+    const uint64_t per = (T.tiles + kScanWG - 1) / kScanWG;
+    const uint64_t t0 = per * t < T.tiles ? per * t : T.tiles;
+    const uint64_t t1 = t0 + per < T.tiles ? t0 + per : T.tiles;
+    uint32_t sum = 0;
+    for (uint64_t k = t0; k < t1; ++k) sum += row[k];
+    part[t] = sum;
     __syncthreads();
-    uint32_t start = 0;
-    for (uint32_t k = 0; k < o; ++k) start += s[k];
-    ctrl->ostart[o] = start;
-    ctrl->ocount[o] = cnt;
-    ctrl->opad[o] = pad;
-    uint32_t at = start;
-    for (uint32_t c = 0; c < kCopies; ++c) {
-        ctrl->cursor[bin * kCopies + c] = at;
-        at += ctrl->hist[bin * kCopies + c];
+    for (uint32_t off = 1; off < kScanWG; off <<= 1) {  // inclusive scan (Hillis-Steele)
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
-    if (o == kBins - 1) ctrl->total_pos = start + pad;
+    uint32_t run = part[t] - sum;
+    for (uint64_t k = t0; k < t1; ++k) {
+        const uint32_t c = row[k];
+        row[k] = run;
+        run += c;
+    }
+    if (t == kScanWG - 1) ctrl->bincount[bin] = part[t];
 }
 
 // Scatter of the tiles wg, wg + n_wg, ... into bin order (one workgroup).
-__device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_t n_id,
+// `start` holds every bin's padded start (longest bins first).
+__device__ __forceinline__ void bin_scatter(const Batch &bt, const uint32_t *__restrict__ thist,
+                                            uint64_t tstride, const uint32_t *start, uint32_t n_id,
                                             unsigned long long *__restrict__ perm,
                                             TxRec *__restrict__ rec, uint32_t *__restrict__ pos_of,
                                             uint64_t wide_min, uint32_t wg, uint32_t n_wg)
@@ -498,7 +512,12 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_
         const DevBlock d = get_block(bt, T, b);
         const uint64_t i0 = (tile - d.tile0) * kTile;
         const uint64_t area_end = d.off[d.n];  // end of the block's message area
-        if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+        if (threadIdx.x < kBins) {
+            cnt[threadIdx.x] = 0;
+            // this tile's first position in each bin: the bin's start plus the
+            // transactions of that bin in earlier tiles
+            base[threadIdx.x] = start[threadIdx.x] + thist[threadIdx.x * tstride + tile];
+        }
         __syncthreads();
         uint32_t bins[kPer], rank[kPer];
         TxRec r[kPer];
@@ -519,11 +538,6 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_
                 rank[k] = atomicAdd(&cnt[bins[k]], 1u);
             }
         }
-        __syncthreads();
-        if (threadIdx.x < kBins && cnt[threadIdx.x])
-            base[threadIdx.x] = atomicAdd(&ctrl->cursor[threadIdx.x * kCopies + wg % kCopies],
-                                          cnt[threadIdx.x]);
-        __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if (bins[k] < kBins) {
@@ -538,13 +552,38 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, Ctrl *ctrl, uint32_
     }
 }
 
-__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl, uint32_t n_id,
+__global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
+                                                     const uint32_t *__restrict__ thist,
+                                                     uint64_t tstride, uint32_t n_id,
                                                      unsigned long long *__restrict__ perm,
                                                      TxRec *__restrict__ rec,
                                                      uint32_t *__restrict__ pos_of, uint64_t wide_min)
 {
-    bin_scatter(bt, ctrl, n_id, perm, rec, pos_of, wide_min < kRecMaxLen ? wide_min : kRecMaxLen,
-                blockIdx.x, gridDim.x);
+    // bin layout from the totals: order o = 63 - bin, longest first, each bin
+    // padded to a multiple of 64; workgroup 0 publishes it for the verify pass
+    __shared__ uint32_t pad[kBins];
+    __shared__ uint32_t start[kBins];
+    const uint32_t o = threadIdx.x;
+    uint32_t c = 0;
+    if (o < kBins) {
+        c = ctrl->bincount[kBins - 1 - o];
+        pad[o] = (c + 63u) & ~63u;
+    }
+    __syncthreads();
+    if (o < kBins) {
+        uint32_t at = 0;
+        for (uint32_t k = 0; k < o; ++k) at += pad[k];
+        start[kBins - 1 - o] = at;
+        if (blockIdx.x == 0) {
+            ctrl->ostart[o] = at;
+            ctrl->ocount[o] = c;
+            ctrl->opad[o] = pad[o];
+            if (o == kBins - 1) ctrl->total_pos = at + pad[o];
+        }
+    }
+    __syncthreads();
+    bin_scatter(bt, thist, tstride, start, n_id, perm, rec, pos_of,
+                wide_min < kRecMaxLen ? wide_min : kRecMaxLen, blockIdx.x, gridDim.x);
 }
 
 // Most wave tiles a persistent verify wave takes per atomic grab.
@@ -707,7 +746,8 @@ __global__ void __launch_bounds__(kWG) k_count(Batch bt)
 // Device-side plan of a graph replay: copies the block descriptors the host
 // wrote into pinned memory, computes their prefixes in the three index
 // spaces (transactions, tiles, wave tiles), publishes the totals, and clears
-// the per-block counts and the binning control words.  One workgroup.
+// the per-block counts and the persistent verify's tile counter.  One
+// workgroup.
 constexpr int kPlanWG = 1024;
 __global__ void __launch_bounds__(kPlanWG) k_plan(const DevBlock *__restrict__ src,
                                                   const uint32_t *__restrict__ src_n,
@@ -720,12 +760,9 @@ __global__ void __launch_bounds__(kPlanWG) k_plan(const DevBlock *__restrict__ s
     uint32_t n = *src_n;
     if (n > max_blocks) n = max_blocks;
     if (t < 3) carry[t] = 0;
-    if (ctrl) {
-        for (uint32_t k = t; k < kBins * kCopies; k += kPlanWG) {
-            ctrl->hist[k] = 0;
-            ctrl->cursor[k] = 0;
-        }
-        if (t == 0) { ctrl->total_pos = 0; ctrl->work = 0; }
+    if (ctrl && t == 0) {
+        ctrl->total_pos = 0;
+        ctrl->work = 0;
     }
     __syncthreads();
     for (uint32_t base = 0; base < n; base += kPlanWG) {
