@@ -243,9 +243,16 @@ ACE_API int ace_verify_batch_noalloc(const ace_keyset *keys, const ace_block *bl
  *                      lower values change no result and only move messages
  *                      onto that path (tests use them to reach it without
  *                      2 GiB messages).
+ *   grab_cap           persistent verify kernel, per length bucket: a wave
+ *                      that last worked on messages of b + 1 inner blocks
+ *                      (b = 63: 64 or more) takes at most grab_cap[b] wave
+ *                      tiles of 64 transactions per atomic grab of the work
+ *                      counter; 0: no cap (8, fewer when the batch is too
+ *                      small for every wave to make four grabs).
  * ace_set_tuning rejects workgroup counts outside 1..64 (derive_wgs_per_cu:
- * 0..64) and wide_min_len outside 1..2^31 - 1.
+ * 0..64), wide_min_len outside 1..2^31 - 1 and grab caps above 8.
  */
+#define ACE_LENGTH_BUCKETS 64
 typedef struct {
     uint64_t binned_min_tx;
     uint32_t verify_wgs_per_cu;
@@ -253,6 +260,7 @@ typedef struct {
     uint32_t auto_persistent;
     uint32_t derive_wgs_per_cu;
     uint64_t wide_min_len;
+    uint8_t grab_cap[ACE_LENGTH_BUCKETS];
 } ace_tuning;
 
 ACE_API int ace_get_tuning(ace_tuning *out);

@@ -67,10 +67,14 @@ class ace_merkle_tree(ctypes.Structure):
                 ("n_leaves", ctypes.c_uint64), ("d_root_out", ctypes.c_void_p)]
 
 
+ACE_LENGTH_BUCKETS = 64
+
+
 class ace_tuning(ctypes.Structure):
     _fields_ = [("binned_min_tx", ctypes.c_uint64), ("verify_wgs_per_cu", ctypes.c_uint32),
                 ("aux_wgs_per_cu", ctypes.c_uint32), ("auto_persistent", ctypes.c_uint32),
-                ("derive_wgs_per_cu", ctypes.c_uint32), ("wide_min_len", ctypes.c_uint64)]
+                ("derive_wgs_per_cu", ctypes.c_uint32), ("wide_min_len", ctypes.c_uint64),
+                ("grab_cap", ctypes.c_uint8 * ACE_LENGTH_BUCKETS)]
 
 
 class ace_profile(ctypes.Structure):
@@ -406,9 +410,12 @@ def profile_read(reset: bool = True) -> dict:
 
 
 def get_tuning() -> dict:
+    """ace_get_tuning as a dict (grab_cap as a list of 64 ints)."""
     t = ace_tuning()
     _check(load().ace_get_tuning(ctypes.byref(t)))
-    return {k: getattr(t, k) for k, _ in ace_tuning._fields_}
+    out = {k: getattr(t, k) for k, _ in ace_tuning._fields_}
+    out["grab_cap"] = list(out["grab_cap"])
+    return out
 
 
 def default_tuning() -> dict:
@@ -422,7 +429,11 @@ def set_tuning(**kw) -> dict:
     old = get_tuning()
     new = dict(old)
     new.update(kw)
-    t = ace_tuning(*[int(new[k]) for k, _ in ace_tuning._fields_])
+    caps = [int(c) for c in new.pop("grab_cap")]
+    if len(caps) != ACE_LENGTH_BUCKETS:
+        raise ValueError("grab_cap needs %d entries" % ACE_LENGTH_BUCKETS)
+    t = ace_tuning(*[int(new[k]) for k, _ in ace_tuning._fields_[:-1]],
+                   (ctypes.c_uint8 * ACE_LENGTH_BUCKETS)(*caps))
     _check(load().ace_set_tuning(ctypes.byref(t)))
     return old
 

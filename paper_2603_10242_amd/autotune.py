@@ -11,12 +11,20 @@ installs the fastest through ace_set_tuning:
   should use the persistent kernel at all (auto_persistent);
 * aux_wgs_per_cu: workgroups per CU of the binning and finalize passes;
 * derive_wgs_per_cu: workgroups per CU of the key derivation while it runs on
-  a second stream beside the binning passes (fewer leave room for them).
+  a second stream beside the binning passes (fewer leave room for them);
+* grab_cap, per length bucket (inner block count ranges): wave tiles the
+  persistent verify kernel takes per atomic grab while it works on that
+  bucket, measured on batches drawn from the bucket alone, each against the
+  dispatcher-scheduled kernel on the same batch;
+* graph_flags: the launch form of the batching graph (the dispatcher-
+  scheduled binned kernel, or the persistent one with the tuned caps),
+  whichever replays the 256-block batching workload faster.
 
 One transaction always owns one lane: SHA-256 is a Merkle-Damgard chain, so
-the blocks of one message cannot be split across lanes, and the candidates
-for lanes-per-message > 1 reduce to one lane doing the work while the others
-wait.  The result is stored as JSON keyed by GPU architecture and CU count
+the blocks of one message cannot be split across lanes; splitting one
+compression's round and schedule work between lanes costs more lane
+instructions than it saves in latency (the measured two-lane candidate is
+described with the kernels' design).  The result is stored as JSON keyed by GPU architecture and CU count
 (``tuning_<arch>_<cus>cu.json`` next to this file) and applied by
 ``apply_saved()``.
 
@@ -90,9 +98,31 @@ def _time(fn, reps: int = 5) -> float:
     return best
 
 
+# Length buckets of the persistent kernel's sweep: ranges of the inner block
+# count nb = ceil((L + 9) / 64); the throughput sweep's messages (64..1232 B)
+# have nb 2..20.
+BUCKETS = ((2, 2), (3, 3), (4, 4), (5, 5), (6, 7), (8, 11), (12, 20), (21, 64))
+
+
+def _time_stream(fn, reps: int = 20) -> float:
+    """Mean time of `reps` calls enqueued back to back on the current stream
+    (launch latency hidden behind the previous call, as in a serving loop)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
 def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20,
         write: bool = True, log=print, out_dir: str | None = None,
-        derive_n: int = 16 << 20) -> dict:
+        derive_n: int = 16 << 20, bucket_n: int = 1 << 20) -> dict:
     import torch
 
     from . import ace
@@ -178,11 +208,73 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
         if t < best_der[0]:
             best_der = (t, dpc)
 
+    ace.set_tuning(derive_wgs_per_cu=int(best_der[1]))
+    del dblk, rks, wd
+
+    # 5. per length bucket: the persistent kernel's tiles per grab, on batches
+    # whose messages all fall in the bucket, against the dispatcher-scheduled
+    # kernel on the same batch
+    caps = [0] * 64
+    buckets = []
+    for k, (lo, hi) in enumerate(BUCKETS):
+        lmin, lmax = max(0, 64 * (lo - 1) - 8), 64 * hi - 9
+        nb_n = bucket_n if hi <= 20 else bucket_n // 4   # long messages: fewer of them
+        wb = W.generate("bucket-%d-%d" % (lo, hi), W.SEED_BASE + 40 + k, n=nb_n, n_id=1 << 18,
+                        lengths=lambda r, n, a=lmin, b=lmax: r.integers(a, b + 1, size=n))
+        kb = ace.midstate_keyset(ace.to_device(wb.rev), wb.salt, wb.info)
+        bb = ace.upload_block(wb.msg, wb.off, wb.ids, wb.tags)
+        ws = ace.workspace(ace.verify_workspace_size(kb, [bb], ace.ACE_BUCKETED))
+        row = {"nb": [lo, hi], "n": nb_n,
+               "dispatcher_ms": min(_time_stream(lambda: ace.verify_batch(kb, [bb], ws, ace.ACE_BUCKETED), 10)
+                                    for _ in range(3))}
+        best_cap = (float("inf"), 0)
+        for cap in (1, 2, 4, 8):
+            ace.set_tuning(grab_cap=[cap] * 64)
+            t = min(_time_stream(lambda: ace.verify_batch(kb, [bb], ws,
+                                                          ace.ACE_BUCKETED | ace.ACE_PERSISTENT), 10)
+                    for _ in range(3))
+            row["persistent_cap%d_ms" % cap] = t
+            if t < best_cap[0]:
+                best_cap = (t, cap)
+        row["cap"] = best_cap[1]
+        row["persistent_over_dispatcher"] = best_cap[0] / row["dispatcher_ms"]
+        for nb in range(lo, hi + 1):
+            caps[nb - 1] = best_cap[1]
+        if hi == 64:
+            caps[63] = best_cap[1]
+        buckets.append(row)
+        log("bucket nb %2d..%2d: dispatcher %.3f ms, persistent %s -> cap %d (%.3f of dispatcher)" % (
+            lo, hi, row["dispatcher_ms"],
+            ", ".join("%.3f" % row["persistent_cap%d_ms" % c] for c in (1, 2, 4, 8)), best_cap[1],
+            row["persistent_over_dispatcher"]))
+        del bb, kb, wb, ws
+    ace.set_tuning(grab_cap=caps)
+
+    # 6. the batching graph's launch form on the batching workload itself
+    w4 = W.config4()
+    edges = np.concatenate([[0], np.cumsum(w4.block_sizes)])
+    d4 = ace.to_device(w4.msg)
+    blocks = [ace.upload_block(None, w4.off[a:b + 1], w4.ids[a:b], w4.tags[a:b], msg_dev=d4)
+              for a, b in zip(edges[:-1], edges[1:])]
+    k4 = ace.midstate_keyset(ace.to_device(w4.rev), w4.salt, w4.info)
+    graph_ms = {}
+    for name, gflags in (("dispatcher", ace.ACE_BUCKETED),
+                         ("persistent", ace.ACE_BUCKETED | ace.ACE_PERSISTENT)):
+        g = ace.Graph(k4, max_blocks=len(blocks), max_tx=w4.n, flags=gflags)
+        graph_ms[name] = min(_time_stream(lambda: g.launch(blocks)) for _ in range(3))
+        g.close()
+    graph_flags = (ace.ACE_BUCKETED | ace.ACE_PERSISTENT
+                   if graph_ms["persistent"] < graph_ms["dispatcher"] else ace.ACE_BUCKETED)
+    meas.append({"batching_graph_ms": graph_ms, "n": int(w4.n), "blocks": len(blocks)})
+    log("batching graph: dispatcher-scheduled %.3f ms, persistent %.3f ms -> flags %d" % (
+        graph_ms["dispatcher"], graph_ms["persistent"], graph_flags))
+
     tuning = {"binned_min_tx": int(binned_min), "verify_wgs_per_cu": int(best_wpc),
               "aux_wgs_per_cu": int(best_aux[1]), "auto_persistent": int(best[2]),
-              "derive_wgs_per_cu": int(best_der[1])}
+              "derive_wgs_per_cu": int(best_der[1]), "grab_cap": caps}
     ace.set_tuning(**tuning)
-    result = {"arch": arch, "cus": cus, "tuning": tuning, "lanes_per_message": 1,
+    result = {"arch": arch, "cus": cus, "tuning": tuning, "graph_flags": int(graph_flags),
+              "lanes_per_message": 1, "buckets": buckets,
               "measured": meas, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     if write:
         path = tuning_path(arch, cus)

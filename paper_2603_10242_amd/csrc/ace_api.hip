@@ -77,6 +77,7 @@ ace_tuning g_tune = {
     /* auto_persistent   */ 0,
     /* derive_wgs_per_cu */ 1,
     /* wide_min_len      */ kRecMaxLen,
+    /* grab_cap          */ {0},
 };
 
 ace_tuning tuning()
@@ -380,17 +381,17 @@ void launch_ordered(const Plan &p, unsigned g, hipStream_t s, const Batch &bt, c
 template <bool PT, bool PE, bool AT>
 void launch_binned_t(unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
                      const HkdfParams &hp, Ctrl *ctrl, const unsigned long long *perm,
-                     const TxRec *rec, uint32_t *vperm)
+                     const TxRec *rec, uint32_t *vperm, const GrabCaps &caps)
 {
     hipLaunchKernelGGL((k_verify_binned<PT, PE, AT>), dim3(g), dim3(kWG), 0, s, bt, ks, hp, ctrl,
-                       perm, rec, vperm);
+                       perm, rec, vperm, caps);
 }
 
 void launch_binned(const Plan &p, unsigned g, hipStream_t s, const Batch &bt, const KeySource &ks,
                    const HkdfParams &hp, Ctrl *ctrl, const unsigned long long *perm,
-                   const TxRec *rec, uint32_t *vperm)
+                   const TxRec *rec, uint32_t *vperm, const GrabCaps &caps)
 {
-#define ACE_B(PT, PE, AT) launch_binned_t<PT, PE, AT>(g, s, bt, ks, hp, ctrl, perm, rec, vperm)
+#define ACE_B(PT, PE, AT) launch_binned_t<PT, PE, AT>(g, s, bt, ks, hp, ctrl, perm, rec, vperm, caps)
     if (p.attest) {
         if (p.per_tx) { if (p.persistent) ACE_B(true, true, true); else ACE_B(true, false, true); }
         else { if (p.persistent) ACE_B(false, true, true); else ACE_B(false, false, true); }
@@ -507,7 +508,10 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     {
         const unsigned g = p.persistent ? tn.verify_wgs_per_cu * cus
                                         : grid_for(p.max_pos / 64, kWavesPerWG, 0x7fffffffu);
-        launch_binned(p, g, s, bt, ks, hp, ctrl, perm, rec, vperm);
+        GrabCaps caps;
+        static_assert(sizeof caps.cap == sizeof tn.grab_cap, "one cap per length bucket");
+        memcpy(caps.cap, tn.grab_cap, sizeof caps.cap);
+        launch_binned(p, g, s, bt, ks, hp, ctrl, perm, rec, vperm, caps);
     }
     if ((rc = launch_status("k_verify_binned launch"))) return rc;
     prof_mark(prof, 3, s);
@@ -612,6 +616,9 @@ ACE_API int ace_set_tuning(const ace_tuning *t)
         return fail(ACE_ERR_INVALID_ARG, "workgroups per CU must be in 1..64 (derive: 0..64)");
     if (t->wide_min_len < 1 || t->wide_min_len > kRecMaxLen)
         return fail(ACE_ERR_INVALID_ARG, "wide_min_len must be in 1..2^31 - 1");
+    for (int b = 0; b < ACE_LENGTH_BUCKETS; ++b)
+        if (t->grab_cap[b] > kGrab)
+            return fail(ACE_ERR_INVALID_ARG, "grab_cap[%d] = %u exceeds %u", b, t->grab_cap[b], kGrab);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune = *t;
     return ACE_OK;

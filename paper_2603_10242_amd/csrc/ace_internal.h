@@ -64,6 +64,12 @@ struct Ctrl {
     uint32_t pad_[62];
 };
 
+// Persistent verify kernel: most wave tiles per atomic grab while a wave
+// works on bin b (0: no cap), a kernel argument set from the launch tuning.
+struct GrabCaps {
+    uint8_t cap[kBins];
+};
+
 // HKDF parameters shared by all identities of a keyset (kernel argument).
 struct HkdfParams {
     uint32_t salt_len;

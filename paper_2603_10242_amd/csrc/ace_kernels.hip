@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
                                                        const TxRec *__restrict__ rec,
-                                                       uint32_t *__restrict__ vperm)
+                                                       uint32_t *__restrict__ vperm, GrabCaps caps)
 {
     __shared__ HkdfPrep prep;
     __shared__ uint32_t ostart[kBins], ocount[kBins], oend[kBins];
@@ -642,18 +642,23 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
     uint32_t w = PERSISTENT ? 0u
                             : blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t left = 0;  // persistent: wave tiles left of the last grab
+    uint32_t o_last = 0;  // persistent: bin order of the wave's last tile (longest bin first)
     for (;;) {
         if constexpr (PERSISTENT) {
             if (left == 0) {
+                // the length bucket's cap on tiles per grab (from the launch
+                // tuning; 0 = none), by the bin the wave last worked on
+                const uint32_t cap = caps.cap[kBins - 1 - o_last];
+                const uint32_t g = cap && cap < grab ? cap : grab;
                 // Every lane takes part in the atomic (lane 0 adds the grab, the
                 // others 0) so no divergent branch precedes the readfirstlane:
                 // with the atomic under `if (lane == 0)` the compiler may split
                 // this loop per lane and leave lanes 1..63 re-reading a stale
                 // tile forever.  Grabs of several tiles keep the counter's
                 // same-address atomics few.
-                const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? grab : 0u);
+                const uint32_t v = atomicAdd(&ctrl->work, lane == 0 ? g : 0u);
                 w = __builtin_amdgcn_readfirstlane(v);
-                left = grab;
+                left = g;
             } else {
                 ++w;
             }
@@ -663,6 +668,7 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? (PE
         const uint32_t k0 = w << 6;
         // bin of this wave: number of bins that end at or before k0
         const uint32_t o = __popcll(__ballot(oend[lane] <= k0));
+        o_last = o;
         const uint32_t k = k0 + lane;
         const bool active = k - ostart[o] < ocount[o];
         TxRef t{};
@@ -823,7 +829,7 @@ template __global__ void k_verify_ordered<false, true>(Batch, KeySource, HkdfPar
 #define ACE_BINNED(P, Q, R)                                                                     \
     template __global__ void k_verify_binned<P, Q, R>(Batch, KeySource, HkdfParams, Ctrl *,   \
                                                       const unsigned long long *, const TxRec *, \
-                                                      uint32_t *);
+                                                      uint32_t *, GrabCaps);
 ACE_BINNED(false, false, false)
 ACE_BINNED(false, true, false)
 ACE_BINNED(true, false, false)

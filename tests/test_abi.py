@@ -138,6 +138,25 @@ def test_noalloc_refuses_calls_beyond_its_scratch_array(lib):
     assert lib.ace_verify_batch_noalloc(ctypes.byref(ks), small, 0, 0, None) == ace.ACE_OK
 
 
+def test_tuning_grab_caps_round_trip_and_limits(lib):
+    """The per-bucket grab caps of ace_tuning: set and read back, values above
+    8 refused with the rest of the tuning left as it was."""
+    from paper_2603_10242_amd import ace
+    old = ace.get_tuning()
+    try:
+        caps = [b % 9 for b in range(ace.ACE_LENGTH_BUCKETS)]
+        ace.set_tuning(grab_cap=caps, verify_wgs_per_cu=3)
+        t = ace.get_tuning()
+        assert t["grab_cap"] == caps and t["verify_wgs_per_cu"] == 3
+        with pytest.raises(ace.AceError):
+            ace.set_tuning(grab_cap=[0] * 63 + [9], verify_wgs_per_cu=5)
+        assert ace.get_tuning() == t
+        with pytest.raises(ValueError):
+            ace.set_tuning(grab_cap=[1] * 10)
+    finally:
+        ace.set_tuning(**old)
+
+
 def test_derive_argument_errors(lib):
     from paper_2603_10242_amd import ace
     salt = ctypes.create_string_buffer(b"s" * 32)

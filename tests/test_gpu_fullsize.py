@@ -117,6 +117,17 @@ def test_sweep_persistent_every_grab(ace, sweep16, tuning):
             ace.set_tuning(auto_persistent=0)
             del blk
         assert 8 in grabs and len(grabs) >= 3, grabs
+        # per-bucket caps on tiles per grab (1..8 by inner block count, and
+        # one cap for every bucket) change no result
+        blk = sweep_block(ace, s, s.w.n)
+        for caps in ([1 + (b % 8) for b in range(64)], [1] * 64, [3] * 64):
+            ace.set_tuning(grab_cap=caps)
+            note("persistent, tuning %s, grab caps %s..." % (tuning, caps[:4]))
+            blk.bitmask.fill_(-1)
+            ace.verify_batch(s.rev, [blk], flags=BUCKETED | PERSISTENT)
+            torch.cuda.synchronize()
+            mask, count = blk.result()
+            assert count == s.ocount and np.array_equal(mask, s.omask), caps[:4]
     finally:
         use_tuning(ace, "saved")
 
