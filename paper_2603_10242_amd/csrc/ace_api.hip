@@ -755,7 +755,7 @@ extern "C" {
 
 ACE_API size_t ace_merkle_workspace_size(const ace_merkle_tree *trees, uint32_t n_trees)
 {
-    MerklePlan p;
+    MerklePlan p{};
     if (merkle_plan(trees, n_trees, p) != ACE_OK) return 0;
     return p.bytes;
 }
@@ -764,7 +764,7 @@ ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, voi
                              size_t ws_bytes, void *stream)
 {
     clear_error();
-    MerklePlan p;
+    MerklePlan p{};
     int rc = merkle_plan(trees, n_trees, p);
     if (rc) return rc;
     if (n_trees == 0) return ACE_OK;
@@ -823,7 +823,7 @@ ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, voi
 ACE_API size_t ace_verify_workspace_size(const ace_keyset *keys, const ace_block *blocks,
                                          uint32_t n_blocks, uint32_t flags)
 {
-    Plan p;
+    Plan p{};
     if (make_plan(keys, blocks, n_blocks, flags, p) != ACE_OK) return 0;
     return p.bytes;
 }
@@ -880,7 +880,7 @@ int verify_impl(const ace_keyset *keys, const ace_block *blocks, uint32_t n_bloc
                 void *d_workspace, size_t ws_bytes, uint32_t flags, void *stream, bool attest)
 {
     clear_error();
-    Plan p;
+    Plan p{};
     int rc = make_plan(keys, blocks, n_blocks, flags, p, attest);
     if (rc) return rc;
     if (n_blocks == 0) return ACE_OK;
@@ -952,7 +952,7 @@ ACE_API int ace_verify_batch_noalloc(const ace_keyset *keys, const ace_block *bl
                                      uint32_t n_blocks, uint32_t flags, void *stream)
 {
     clear_error();
-    Plan p;
+    Plan p{};
     int rc = make_plan(keys, blocks, n_blocks, flags, p, false);
     if (rc) return rc;
     if (n_blocks == 0) return ACE_OK;
@@ -1005,7 +1005,7 @@ ACE_API int ace_profile_read(ace_profile *out, int reset)
 ACE_API size_t ace_graph_workspace_size(const ace_keyset *keys, uint32_t max_blocks, uint64_t max_tx,
                                         uint32_t flags)
 {
-    Plan p;
+    Plan p{};
     if (check_keyset(keys, flags, p) != ACE_OK) return 0;
     if (max_blocks == 0 || max_blocks >= (1u << 24) || max_tx > ACE_MAX_TX) return 0;
     layout(keys, max_blocks, max_tx, 0, flags, true, p);
@@ -1018,7 +1018,7 @@ ACE_API int ace_graph_create(const ace_keyset *keys, uint32_t max_blocks, uint64
     clear_error();
     if (!out) return fail(ACE_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    Plan p;
+    Plan p{};
     int rc = check_keyset(keys, flags, p);
     if (rc) return rc;
     if (max_blocks == 0) return fail(ACE_ERR_INVALID_ARG, "max_blocks is 0");

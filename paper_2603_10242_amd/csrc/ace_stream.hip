@@ -606,7 +606,7 @@ ACE_API int ace_stream_create(const ace_keyset *keys, void *d_arena, size_t aren
     clear_error();
     if (!out) return fail(ACE_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    Plan p;
+    Plan p{};
     int rc = check_keyset(keys, 0, p);
     if (rc) return rc;
     if (flags & ~(uint32_t)ACE_STREAM_PLAIN) return fail(ACE_ERR_INVALID_ARG, "unknown flags");
