@@ -186,12 +186,24 @@ class DeviceBlock:
     count: torch.Tensor     # int64 [1]
     n: int
 
+    def __setattr__(self, name, value):
+        # a reassigned field invalidates the validated C descriptors below
+        object.__setattr__(self, name, value)
+        self.__dict__.pop("_structs", None)
+
     def struct(self, record_bytes: int = 32) -> ace_block:
-        n = self.n
-        return ace_block(_ptr(self.msg, 0, "msg"), _ptr(self.off, 8 * (n + 1), "off"),
-                         _ptr(self.ids, 4 * n, "ids"), _ptr(self.tags, record_bytes * n, "tags"), n,
-                         _ptr(self.bitmask, 4 * ((n + 31) // 32), "bitmask"),
-                         _ptr(self.count, 8, "count"))
+        """The C descriptor (checked once per record width and kept until a field
+        is reassigned; tensors must not be resized in place meanwhile)."""
+        cache = self.__dict__.setdefault("_structs", {})
+        s = cache.get(record_bytes)
+        if s is None:
+            n = self.n
+            s = ace_block(_ptr(self.msg, 0, "msg"), _ptr(self.off, 8 * (n + 1), "off"),
+                          _ptr(self.ids, 4 * n, "ids"), _ptr(self.tags, record_bytes * n, "tags"), n,
+                          _ptr(self.bitmask, 4 * ((n + 31) // 32), "bitmask"),
+                          _ptr(self.count, 8, "count"))
+            cache[record_bytes] = s
+        return s
 
     def result(self) -> tuple[np.ndarray, int]:
         m = self.bitmask.cpu().numpy().view(np.uint32).copy()
