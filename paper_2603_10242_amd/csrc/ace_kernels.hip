@@ -193,56 +193,77 @@ __device__ __forceinline__ LaneGeom lane_geom(bool live, const TxRef &t)
     return g;
 }
 
-// The message blocks of one lane, chained onto S.  Windows are loaded two
-// blocks at a time where the second block exists: one 33-dword load covers
-// blocks b and b + 1 (two cache lines instead of the three that two separate
-// 17-dword windows touch on average), and block b + 1 takes its window from
-// the registers already holding it.  Lanes of one wave share their block
-// count (same bin), so the branches below are uniform in the binned kernels.
+// Loads of the windows of N consecutive blocks from q: 16 N + 1 dwords.
+template <int N, int K>
+__device__ __forceinline__ void load_windows(uint32_t (&D)[16 * K + 1], const uint32_t *q)
+{
+#pragma unroll
+    for (int c = 0; c < 4 * N; ++c) {
+        const U4 v = load16(q + 4 * c);
+        D[4 * c] = v.x; D[4 * c + 1] = v.y; D[4 * c + 2] = v.z; D[4 * c + 3] = v.w;
+    }
+    D[16 * N] = load32(q + 16 * N);
+}
+
+// Schedule words of the window in slot S (dwords 16 S .. 16 S + 16).
+template <int S, int K>
+__device__ __forceinline__ void window_words(uint32_t (&W)[16], const uint32_t (&D)[16 * K + 1],
+                                             uint32_t sel)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[16 * S + j + 1], D[16 * S + j], sel);
+}
+
+// The message blocks of one lane, chained onto S.  The windows of up to K
+// consecutive blocks come in one load of 16 K + 1 dwords (K blocks touch
+// about 1 + (64 K + 3) / 128 cache lines together instead of about 1.5 each),
+// and the following blocks take their windows from the registers holding
+// them.  A group of K windows is loaded when K blocks remain, else a pair,
+// else one window; a group may read at most 76 bytes past the message end
+// (its last block exists, so at least 64 (K - 2) + 56 message bytes are
+// left), which the caller allows (overread_ok) or the message covers.  Lanes
+// of one wave share their block count (same bin), so the branches below are
+// uniform in the binned kernels.
+template <int K>
 __device__ __forceinline__ void message_blocks(State &S, bool live, bool overread_ok, const LaneGeom &g,
                                                int64_t L)
 {
+    static_assert(K >= 2 && K <= 3, "groups of two or three windows");
     // a do-while with the wave's vote at the end: with the vote at the top the
     // state was copied twice per block
     const uint32_t *q = g.A0;  // dword 16 b of the message area, advanced per block
     int64_t rb = L;            // message bytes from this block on
     uint32_t b = 0;
     bool run = live;           // a live lane has at least one block
-    bool held = false;         // D[16..32] holds this block's window (loaded with the previous one)
-    uint32_t D[33];
+    uint32_t avail = 0;        // windows of this and later blocks already in D
+    uint32_t slot = 0;         // slot of this block's window in D
+    uint32_t D[16 * K + 1];
     if (__ballot(run)) do {
         if (run) {
             uint32_t W[16];
-            if (!held) {
-                // windows of blocks b and b + 1 in one 33-dword load when block b + 1
-                // exists: at most 76 bytes past the message end (rb >= 56), or none
-                const bool pair = b + 1 < g.nb && (overread_ok || rb >= 132);
-                if (pair) {
-                    const U4 v0 = load16(q), v1 = load16(q + 4), v2 = load16(q + 8), v3 = load16(q + 12);
-                    const U4 v4 = load16(q + 16), v5 = load16(q + 20), v6 = load16(q + 24), v7 = load16(q + 28);
-                    D[0] = v0.x; D[1] = v0.y; D[2] = v0.z; D[3] = v0.w;
-                    D[4] = v1.x; D[5] = v1.y; D[6] = v1.z; D[7] = v1.w;
-                    D[8] = v2.x; D[9] = v2.y; D[10] = v2.z; D[11] = v2.w;
-                    D[12] = v3.x; D[13] = v3.y; D[14] = v3.z; D[15] = v3.w;
-                    D[16] = v4.x; D[17] = v4.y; D[18] = v4.z; D[19] = v4.w;
-                    D[20] = v5.x; D[21] = v5.y; D[22] = v5.z; D[23] = v5.w;
-                    D[24] = v6.x; D[25] = v6.y; D[26] = v6.z; D[27] = v6.w;
-                    D[28] = v7.x; D[29] = v7.y; D[30] = v7.z; D[31] = v7.w;
-                    D[32] = load32(q + 32);
+            if (avail == 0) {
+                const uint32_t left = g.nb - b;
+                uint32_t m = 1;
+                if (left >= (uint32_t)K && (overread_ok || rb >= 64 * (K - 1) + 68)) m = K;
+                else if (left >= 2 && (overread_ok || rb >= 132)) m = 2;
+                if (m == (uint32_t)K) {
+                    load_windows<K, K>(D, q);
+                } else if (m == 2) {
+                    load_windows<2, K>(D, q);
                 } else {
                     uint32_t E[17];
                     load_window(E, q, rb, overread_ok, g.A0, g.last, b);
 #pragma unroll
                     for (int j = 0; j < 17; ++j) D[j] = E[j];
                 }
-#pragma unroll
-                for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], g.sel);
-                held = pair;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 17], D[j + 16], g.sel);
-                held = false;
+                avail = m;
+                slot = 0;
             }
+            if (slot == 0) window_words<0, K>(W, D, g.sel);
+            else if (K == 2 || slot == 1) window_words<1, K>(W, D, g.sel);
+            else window_words<K - 1, K>(W, D, g.sel);
+            ++slot;
+            --avail;
             if (rb < 64) {
                 // padding: word jf holds byte rb (the 0x80 marker) after its c
                 // message bytes; earlier words are message, later ones zero
@@ -382,7 +403,9 @@ __device__ __forceinline__ bool verify_lane(bool live, const TxRef &t, const Hkd
     // the payload digest, from the initial value
     State S = ATTEST ? initial_state() : ipad;
     const LaneGeom g = lane_geom<ATTEST>(live, t);
-    message_blocks(S, live, t.overread_ok, g, (int64_t)t.L);
+    // three windows per load where the registers allow it; the per-transaction
+    // derivation's state leaves room for two
+    message_blocks<PER_TX_KEYS ? 2 : 3>(S, live, t.overread_ok, g, (int64_t)t.L);
     uint32_t C[check_words<ATTEST>()];
 #pragma unroll
     for (int i = 0; i < check_words<ATTEST>(); ++i) C[i] = 0;
@@ -412,7 +435,7 @@ __device__ __forceinline__ bool load_tx(const DevBlock &d, uint64_t i, const Key
 // one block; the ballot is that block's two bitmask words.
 // ------------------------------------------------------------------------------------------
 template <bool PER_TX_KEYS, bool ATTEST>
-__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : 5) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
+__global__ void __launch_bounds__(kWG) ACE_WAVES(4) k_verify_ordered(Batch bt, KeySource ks, HkdfParams hp)
 {
     __shared__ HkdfPrep prep;
     if constexpr (PER_TX_KEYS) {
@@ -646,7 +669,7 @@ __device__ __forceinline__ bool binned_tx(const Batch &bt, const Totals &T, cons
 }
 
 template <bool PER_TX_KEYS, bool PERSISTENT, bool ATTEST>
-__global__ void __launch_bounds__(kWG) ACE_WAVES(PER_TX_KEYS ? 4 : (ATTEST ? 5 : 6)) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
+__global__ void __launch_bounds__(kWG) ACE_WAVES(4) k_verify_binned(Batch bt, KeySource ks, HkdfParams hp,
                                                        Ctrl *ctrl,
                                                        const unsigned long long *__restrict__ perm,
                                                        const TxRec *__restrict__ rec,
