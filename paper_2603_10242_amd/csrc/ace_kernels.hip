@@ -221,9 +221,12 @@ __device__ __forceinline__ void window_words(uint32_t (&W)[16], const uint32_t (
 // them.  A group of K windows is loaded when K blocks remain, else a pair,
 // else one window; a group may read at most 76 bytes past the message end
 // (its last block exists, so at least 64 (K - 2) + 56 message bytes are
-// left), which the caller allows (overread_ok) or the message covers.  Lanes
-// of one wave share their block count (same bin), so the branches below are
-// uniform in the binned kernels.
+// left), which the caller allows (overread_ok) or the message covers.  The
+// first group is loaded before the block loop, so its loads are in flight
+// together with the caller's midstate loads (inside the loop the compiler
+// waited for all outstanding loads before issuing a group's).  Lanes of one
+// wave share their block count (same bin), so the branches below are uniform
+// in the binned kernels.
 template <int K>
 __device__ __forceinline__ void message_blocks(State &S, bool live, bool overread_ok, const LaneGeom &g,
                                                int64_t L)
@@ -235,9 +238,25 @@ __device__ __forceinline__ void message_blocks(State &S, bool live, bool overrea
     int64_t rb = L;            // message bytes from this block on
     uint32_t b = 0;
     bool run = live;           // a live lane has at least one block
-    uint32_t avail = 0;        // windows of this and later blocks already in D
     uint32_t slot = 0;         // slot of this block's window in D
     uint32_t D[16 * K + 1];
+    uint32_t avail = 0;        // windows of this and later blocks already in D
+    if (run) {
+        // the first group before the loop: its loads go out with the midstate loads
+        const uint32_t left = g.nb;
+        uint32_t m = 1;
+        if (left >= (uint32_t)K && (overread_ok || rb >= 64 * (K - 1) + 68)) m = K;
+        else if (left >= 2 && (overread_ok || rb >= 132)) m = 2;
+        if (m == (uint32_t)K) load_windows<K, K>(D, q);
+        else if (m == 2) load_windows<2, K>(D, q);
+        else {
+            uint32_t E[17];
+            load_window(E, q, rb, overread_ok, g.A0, g.last, 0);
+#pragma unroll
+            for (int j = 0; j < 17; ++j) D[j] = E[j];
+        }
+        avail = m;
+    }
     if (__ballot(run)) do {
         if (run) {
             uint32_t W[16];
