@@ -922,6 +922,8 @@ def main() -> int:
     bytes_tx = L.astype(np.float64) + 32 + 4 + 8 + 64 + 1.0 / 8
     verify_bytes = float(bytes_tx.sum())
     step_comp = verify_comp + derive_comp
+    traffic = counter_traffic() if (args.n == 16 << 20 and args.mode == "binned"
+                                    and args.keys == "recomputed" and args.ids == "uniform") else None
     result = {
         "metric": METRIC,
         "value": w.n / (ms_per_step / 1e3),
@@ -950,11 +952,13 @@ def main() -> int:
             "peak": PEAK_INT32_TOPS,
             "unit": "T int32 lane-instr/s",
             "frac": achieved / PEAK_INT32_TOPS,
-            "traffic": counter_traffic() if (args.n == 16 << 20 and args.mode == "binned"
-                                              and args.keys == "recomputed"
-                                              and args.ids == "uniform") else None,
+            "traffic": traffic,
             "per_launch": "%d compressions x %d VALU instr" % (verify_comp, I_REF),
             "avg_ms": verify_s * 1e3,
+            "gcompressions_per_s": verify_comp / verify_s / 1e9,
+            # the counted HBM bytes over the live launch time, against the 8 TB/s peak
+            "hbm_gbs": traffic / verify_s / 1e9 if traffic else None,
+            "hbm_frac": traffic / verify_s / 1e9 / HBM_PEAK_GBS if traffic else None,
         },
         "pct_peak_int32_valu_step": 100.0 * step_comp * I_REF / (ms_per_step / 1e3) / 1e12
                                     / PEAK_INT32_TOPS,
