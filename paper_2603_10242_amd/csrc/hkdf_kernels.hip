@@ -160,20 +160,27 @@ __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], 
 // ------------------------------------------------------------------------------------------
 // k_derive: one identity per lane.
 // ------------------------------------------------------------------------------------------
-// Key and midstates of identity j under the prepared parameter set; outputs
-// go to row `row` of key_out / mid_out.
-__device__ __forceinline__ void derive_identity(const uint8_t *__restrict__ rev, uint32_t n_id,
-                                                uint32_t j, uint64_t row, const HkdfPrep &prep,
-                                                uint8_t *__restrict__ key_out,
-                                                uint32_t *__restrict__ mid_out)
+// Root entropy of identity j as loaded (little-endian words).
+struct RevRaw {
+    U4 a, b;
+};
+
+__device__ __forceinline__ RevRaw load_rev(const uint8_t *__restrict__ rev, uint32_t j)
 {
-    const bool live = j < n_id;
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(rev + 32ull * j);
+    return RevRaw{load16(p), load16(p + 4)};
+}
+
+// Key and midstates of an identity from its root entropy x (ignored unless
+// live); outputs go to row `row` of key_out / mid_out.
+__device__ __forceinline__ void derive_store(bool live, const RevRaw &x, uint64_t row,
+                                             const HkdfPrep &prep, uint8_t *__restrict__ key_out,
+                                             uint32_t *__restrict__ mid_out)
+{
     uint32_t rv[8];
     if (live) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(rev + 32ull * j);
-        const U4 a = load16(p), b = load16(p + 4);
-        rv[0] = bswap32(a.x); rv[1] = bswap32(a.y); rv[2] = bswap32(a.z); rv[3] = bswap32(a.w);
-        rv[4] = bswap32(b.x); rv[5] = bswap32(b.y); rv[6] = bswap32(b.z); rv[7] = bswap32(b.w);
+        rv[0] = bswap32(x.a.x); rv[1] = bswap32(x.a.y); rv[2] = bswap32(x.a.z); rv[3] = bswap32(x.a.w);
+        rv[4] = bswap32(x.b.x); rv[5] = bswap32(x.b.y); rv[6] = bswap32(x.b.z); rv[7] = bswap32(x.b.w);
     } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) rv[i] = 0;
@@ -198,14 +205,26 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive(const uint8_t *__re
                                                 uint8_t *__restrict__ key_out,
                                                 uint32_t *__restrict__ mid_out, HkdfParams hp)
 {
+    // grid-stride: a grid smaller than n_id / kWG leaves CU slots to kernels
+    // running beside it on another stream.  Each lane's next identity is
+    // loaded before the current one is derived (the first one before the
+    // parameter set is prepared), so with one wave per SIMD the load's
+    // latency is not added to every identity.
+    const uint64_t stride = (uint64_t)gridDim.x * kWG;
+    uint64_t j = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    RevRaw next{};
+    if (j < n_id) next = load_rev(rev, (uint32_t)j);
     __shared__ HkdfPrep prep;
     if (threadIdx.x < 64) hkdf_prepare(hp, prep);
     __syncthreads();
-    // grid-stride: a grid smaller than n_id / kWG leaves CU slots to kernels
-    // running beside it on another stream
-    for (uint32_t base = blockIdx.x * kWG; base < n_id; base += gridDim.x * kWG) {
-        const uint32_t j = base + threadIdx.x;
-        derive_identity(rev, n_id, j, j, prep, key_out, mid_out);
+    // the first identity's words are waited for here, so that in the loop the
+    // compiler waits only for the prefetch and not for the stores after it
+    asm volatile("" :: "v"(next.a.x), "v"(next.a.y), "v"(next.a.z), "v"(next.a.w), "v"(next.b.x),
+                 "v"(next.b.y), "v"(next.b.z), "v"(next.b.w));
+    for (uint64_t base = (uint64_t)blockIdx.x * kWG; base < n_id; base += stride, j += stride) {
+        const RevRaw cur = next;
+        if (j + stride < n_id) next = load_rev(rev, (uint32_t)(j + stride));
+        derive_store(j < n_id, cur, j, prep, key_out, mid_out);
     }
 }
 
@@ -221,7 +240,10 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(5) k_derive_multi(const uint8_t
     if (threadIdx.x < 64) hkdf_prepare(mp.s[y], prep);
     __syncthreads();
     const uint32_t j = blockIdx.x * kWG + threadIdx.x;
-    derive_identity(rev, n_id, j, (uint64_t)(mp.first + y) * n_id + j, prep, key_out, mid_out);
+    const bool live = j < n_id;
+    RevRaw x{};
+    if (live) x = load_rev(rev, j);
+    derive_store(live, x, (uint64_t)(mp.first + y) * n_id + j, prep, key_out, mid_out);
 }
 
 }  // namespace ace
