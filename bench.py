@@ -182,21 +182,28 @@ def measured_valu_rate(ace, torch) -> dict:
 
 
 def time_calls(fn, steps: int, warmup: int):
-    """Per-call wall times (ms) of fn() bracketed by stream events, after warmup."""
+    """After warmup: the mean wall time (ms) of `steps` calls of fn() enqueued
+    back to back between two synchronizations, and then, from a second run of
+    `steps` calls with a stream event pair around each, every call's own time
+    (the latency percentiles; the events between calls are kept out of the
+    throughput run)."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    t0 = time.perf_counter()
     for k in range(steps):
         starts[k].record(stream)
         fn()
         ends[k].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ev = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     return wall * 1e3 / steps, ev
 
@@ -870,20 +877,29 @@ def main() -> int:
                 return 1
             log("warmup step 0 bit-exact with the generator's truth mask (%d valid)" % count)
 
-    # value: K plain calls (no stage events inside the library)
+    # value: K plain calls back to back between two synchronizations (no stage
+    # events inside the library, no events between the calls); then K more,
+    # each between two stream events, for the step latency percentiles
     stream = torch.cuda.current_stream()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for k in range(args.steps):
+        ace.verify_batch(ks, [blk], ws, flags)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    mask, count = blk.result()
+    if count != int(w.truth.sum()) or not np.array_equal(mask, w.truth_bitmask()):
+        log("RESULT MISMATCH after timing")
+        return 1
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     for k in range(args.steps):
         starts[k].record(stream)
         ace.verify_batch(ks, [blk], ws, flags)
         ends[k].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    ms_per_step = wall * 1e3 / args.steps
     log("timed %d steps: %.3f ms/step (events p50 %.3f, p99 %.3f)"
         % (args.steps, ms_per_step, np.percentile(step_ms, 50), np.percentile(step_ms, 99)))
     mask, count = blk.result()
