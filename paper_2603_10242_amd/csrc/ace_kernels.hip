@@ -758,8 +758,9 @@ __global__ void __launch_bounds__(kWG) ACE_WAVES(4) k_verify_binned(Batch bt, Ke
     }
 }
 
-// Bin-order verdicts back to input order: one lane per transaction, wave64
-// ballot per 64 transactions, one count atomic per workgroup and block.
+// Bin-order verdicts back to input order: one lane per transaction gathers
+// its bit through its bin-order position, a wave64 ballot per 64
+// transactions gives two bitmask words (k_count then adds up the counts).
 __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__restrict__ pos_of,
                                                   const uint32_t *__restrict__ vperm)
 {
