@@ -168,6 +168,37 @@ def cpu_baseline(w, seconds: float, runs: int = 5) -> dict:
             "host": host}
 
 
+def openssl_context(w, threads: int, runs: int = 3) -> dict:
+    """Context beside the oracle: the same step with OpenSSL (the workload
+    generator's client library, which uses the CPU's SHA extensions where it
+    has them): HKDF for every identity, then HMAC-SHA256 of every transaction,
+    on `threads` threads (median of `runs`), and one thread's cost per
+    transaction.  The recomputed tags are checked against the generator's
+    truth mask once, outside the timing."""
+    from paper_2603_10242_amd import workload as W
+    steps = []
+    for r in range(runs):
+        t = time.perf_counter()
+        keys = W.client_keys(w.rev, w.salt, w.info, threads)
+        tags = W.client_sign(keys, w.msg, w.off, w.ids, threads)
+        steps.append(time.perf_counter() - t)
+        if r == 0:
+            ok = np.all(tags == w.tags, axis=1)
+            if not np.array_equal(ok, w.truth):
+                raise SystemExit("OpenSSL recomputation disagrees with the generator's truth mask")
+        del tags
+    one = min(w.n, 200_000)
+    single = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        W.client_sign(keys, w.msg, w.off[: one + 1], w.ids[:one], 1)
+        single.append((time.perf_counter() - t) / one * 1e6)
+    step_s = float(np.median(steps))
+    return {"value": w.n / step_s, "unit": "attestations/s", "cores": threads,
+            "kind": "OpenSSL HKDF + HMAC-SHA256 (context, not the oracle)",
+            "step_s_runs": steps, "single_thread_us_per_tx": float(np.median(single))}
+
+
 def measured_valu_rate(ace, torch) -> dict:
     """The device's INT32 VALU issue rate from the library's probe kernel, beside
     the peak the roofline uses (the probe runs after the timed steps)."""
@@ -1000,6 +1031,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (about %.0f s)" % args.cpu_seconds)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        result["cpu_baseline"]["openssl_context"] = openssl_context(w, result["cpu_baseline"]["cores"])
     del blk, rev, ks, ws, w
     torch.cuda.empty_cache()
     if not args.no_batching:

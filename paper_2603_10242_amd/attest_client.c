@@ -36,14 +36,20 @@ static void derive_range(job_t *j)
     EVP_KDF *kdf = EVP_KDF_fetch(NULL, "HKDF", NULL);
     EVP_KDF_CTX *ctx = kdf ? EVP_KDF_CTX_new(kdf) : NULL;
     if (!ctx) { j->status = -1; EVP_KDF_free(kdf); return; }
-    for (uint64_t i = j->lo; i < j->hi; ++i) {
-        OSSL_PARAM p[5], *q = p;
-        *q++ = OSSL_PARAM_construct_utf8_string(OSSL_KDF_PARAM_DIGEST, (char *)"SHA256", 0);
-        *q++ = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_KEY, (void *)(j->rev + 32 * i), 32);
-        if (j->slen)
-            *q++ = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_SALT, (void *)j->salt, j->slen);
-        *q++ = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_INFO, (void *)j->info, j->ilen);
-        *q = OSSL_PARAM_construct_end();
+    /* digest, salt and info are the same for every identity and set once (the
+       digest named in every call was looked up again each time, under a lock
+       the threads share); each derivation passes only its key */
+    OSSL_PARAM c[4], *q = c;
+    *q++ = OSSL_PARAM_construct_utf8_string(OSSL_KDF_PARAM_DIGEST, (char *)"SHA256", 0);
+    if (j->slen)
+        *q++ = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_SALT, (void *)j->salt, j->slen);
+    *q++ = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_INFO, (void *)j->info, j->ilen);
+    *q = OSSL_PARAM_construct_end();
+    if (EVP_KDF_CTX_set_params(ctx, c) <= 0) j->status = -1;
+    for (uint64_t i = j->lo; i < j->hi && !j->status; ++i) {
+        OSSL_PARAM p[2];
+        p[0] = OSSL_PARAM_construct_octet_string(OSSL_KDF_PARAM_KEY, (void *)(j->rev + 32 * i), 32);
+        p[1] = OSSL_PARAM_construct_end();
         if (EVP_KDF_derive(ctx, j->keys_out + 32 * i, 32, p) <= 0) { j->status = -2; break; }
     }
     EVP_KDF_CTX_free(ctx);
@@ -58,12 +64,15 @@ static void sign_range(job_t *j)
     OSSL_PARAM p[2];
     p[0] = OSSL_PARAM_construct_utf8_string(OSSL_MAC_PARAM_DIGEST, (char *)"SHA256", 0);
     p[1] = OSSL_PARAM_construct_end();
+    /* the digest is set once: passed to every init, it was looked up again each
+       time, under a lock the threads share */
+    if (EVP_MAC_CTX_set_params(ctx, p) <= 0) { j->status = -1; EVP_MAC_CTX_free(ctx); EVP_MAC_free(mac); return; }
     for (uint64_t i = j->lo; i < j->hi; ++i) {
         size_t outl = 0;
         const uint8_t *key = j->keys + 32 * (size_t)j->key_index[i];
         const uint8_t *m = j->msg + j->off[i];
         size_t len = (size_t)(j->off[i + 1] - j->off[i]);
-        if (EVP_MAC_init(ctx, key, 32, p) <= 0 || EVP_MAC_update(ctx, m, len) <= 0 ||
+        if (EVP_MAC_init(ctx, key, 32, NULL) <= 0 || EVP_MAC_update(ctx, m, len) <= 0 ||
             EVP_MAC_final(ctx, j->tags_out + 32 * i, &outl, 32) <= 0 || outl != 32) {
             j->status = -2;
             break;
