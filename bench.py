@@ -195,7 +195,8 @@ def openssl_context(w, threads: int, runs: int = 3) -> dict:
         single.append((time.perf_counter() - t) / one * 1e6)
     step_s = float(np.median(steps))
     return {"value": w.n / step_s, "unit": "attestations/s", "cores": threads,
-            "kind": "OpenSSL HKDF + HMAC-SHA256 (context, not the oracle)",
+            "kind": "OpenSSL EVP HKDF + HMAC-SHA256 per call (context, not the oracle; its "
+                    "threads share the library's internal locks)",
             "step_s_runs": steps, "single_thread_us_per_tx": float(np.median(single))}
 
 
