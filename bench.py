@@ -216,9 +216,9 @@ def measured_valu_rate(ace, torch) -> dict:
 def time_calls(fn, steps: int, warmup: int):
     """After warmup: the mean wall time (ms) of `steps` calls of fn() enqueued
     back to back between two synchronizations, and then, from a second run of
-    `steps` calls with a stream event pair around each, every call's own time
-    (the latency percentiles; the events between calls are kept out of the
-    throughput run)."""
+    max(steps, 50) calls with a stream event pair around each, every call's
+    own time (the latency percentiles; the events between calls are kept out
+    of the throughput run)."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -229,9 +229,10 @@ def time_calls(fn, steps: int, warmup: int):
         fn()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    for k in range(steps):
+    n_lat = max(steps, 50)   # enough calls for a p99 that is not simply the maximum
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    for k in range(n_lat):
         starts[k].record(stream)
         fn()
         ends[k].record(stream)
@@ -924,9 +925,10 @@ def main() -> int:
     if count != int(w.truth.sum()) or not np.array_equal(mask, w.truth_bitmask()):
         log("RESULT MISMATCH after timing")
         return 1
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    for k in range(args.steps):
+    n_lat = max(args.steps, 50)   # enough steps for a p99 that is not simply the maximum
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    for k in range(n_lat):
         starts[k].record(stream)
         ace.verify_batch(ks, [blk], ws, flags)
         ends[k].record(stream)
@@ -1014,6 +1016,7 @@ def main() -> int:
         "gcompressions_per_s": step_comp / (ms_per_step / 1e3) / 1e9,
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
+        "latency_steps": int(len(step_ms)),
         "ms_per_step_traced": traced_ms,
         # in the binned form with keys derived in the call, the derivation runs
         # on a second stream beside the binning passes: bin_ms covers both and
