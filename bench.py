@@ -796,7 +796,7 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=16 << 20, help="transactions per batch")
     ap.add_argument("--n-id", type=int, default=1 << 20, help="identities in the registry")
     ap.add_argument("--ids", choices=["uniform", "zipf"], default="uniform")
