@@ -502,36 +502,81 @@ __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
     }
 }
 
-// Length used for binning: transactions that cannot be valid hash nothing.
-__device__ __forceinline__ uint64_t tx_length(const DevBlock &d, uint64_t i, uint32_t n_id)
+// A tile's offsets and identities as the binning passes read them: thread t
+// holds transactions i0 + t + k kWG, k < kPer (those past the block's end
+// are not loaded).  A workgroup loads its next tile into a second TileTx
+// while it bins the current one, so its loads stay in flight across the
+// tile's LDS atomics, barriers and stores (with one tile at a time, a pass
+// over small tiles was bound by how fast workgroups could be started).
+constexpr int kPer = kTile / kWG;
+
+struct TileTx {
+    uint64_t a[kPer], e[kPer];
+    uint32_t who[kPer];
+};
+
+// Every lane loads (past the block's last transaction it reloads that one,
+// which the caller then ignores): with loads under a branch the compiler
+// waited for all of them, the next tile's included, before using any.
+// (Global, not flat, loads: they count only against the vector memory
+// counter, so LDS accesses do not wait for them.)
+typedef const __attribute__((address_space(1))) uint64_t *gptr64;
+
+__device__ __forceinline__ void load_tile_tx(const DevBlock &d, uint64_t i0, TileTx &x)
 {
-    const uint64_t a = d.off[i], e = d.off[i + 1];
-    return (a <= e && d.id[i] < n_id) ? e - a : 0;
+    const gptr64 off = (gptr64)d.off;
+    const gptr id = (gptr)d.id;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+        const uint64_t j = i < d.n ? i : d.n - 1;  // a tile's block holds at least one transaction
+        x.a[k] = off[j];
+        x.e[k] = off[j + 1];
+        x.who[k] = id[j];
+    }
+}
+
+// Length used for binning: transactions that cannot be valid hash nothing.
+__device__ __forceinline__ uint64_t tx_length(uint64_t a, uint64_t e, uint32_t who, uint32_t n_id)
+{
+    return (a <= e && who < n_id) ? e - a : 0;
 }
 
 __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, uint32_t *__restrict__ thist,
                                                    uint64_t tstride, uint32_t n_id)
 {
-    constexpr int kPer = kTile / kWG;
     __shared__ uint32_t h[kBins];
     const Totals T = totals(bt);
-    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
+    if (blockIdx.x >= T.tiles) return;  // the whole workgroup
+    // Two buffers used in turn (the loop body twice, no copies between them):
+    // the tile in one is binned while the next tile's loads fill the other.
+    TileTx xa, xb;
+    DevBlock da = get_block(bt, T, find_block<0>(bt, T, blockIdx.x)), db;
+    uint64_t ta = blockIdx.x, tb;
+    load_tile_tx(da, (ta - da.tile0) * kTile, xa);
+    // bins tile t (block d, loads x) while tile `nt` (the last tile: t again,
+    // unused) loads into y; returns whether there was a next tile
+    auto step = [&](const TileTx &x, const DevBlock &d, uint64_t t, TileTx &y, DevBlock &dn,
+                    uint64_t &nt) -> bool {
+        const bool more = t + gridDim.x < T.tiles;  // uniform
+        nt = more ? t + gridDim.x : t;
+        dn = get_block(bt, T, find_block<0>(bt, T, nt));
+        load_tile_tx(dn, (nt - dn.tile0) * kTile, y);
         if (threadIdx.x < kBins) h[threadIdx.x] = 0;
         __syncthreads();
-        const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
-        const uint64_t i0 = (tile - d.tile0) * kTile;
-        uint32_t bins[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {  // all loads first, then the counting
-            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
-            bins[k] = i < d.n ? bin_of_length(tx_length(d, i, n_id)) : kBins;
-        }
+        const uint64_t i0 = (t - d.tile0) * kTile;
 #pragma unroll
         for (int k = 0; k < kPer; ++k)
-            if (bins[k] < kBins) atomicAdd(&h[bins[k]], 1u);
+            if (i0 + threadIdx.x + (uint64_t)k * kWG < d.n)
+                atomicAdd(&h[bin_of_length(tx_length(x.a[k], x.e[k], x.who[k], n_id))], 1u);
         __syncthreads();
-        if (threadIdx.x < kBins) thist[threadIdx.x * tstride + tile] = h[threadIdx.x];
+        if (threadIdx.x < kBins) thist[threadIdx.x * tstride + t] = h[threadIdx.x];
         __syncthreads();
+        return more;
+    };
+    for (;;) {
+        if (!step(xa, da, ta, xb, db, tb)) break;
+        if (!step(xb, db, tb, xa, da, ta)) break;
     }
 }
 
@@ -569,44 +614,62 @@ __global__ void __launch_bounds__(kScanWG) k_bin_scan(Batch bt, Ctrl *ctrl,
     if (t == kScanWG - 1) ctrl->bincount[bin] = part[t];
 }
 
-// Scatter of the tiles wg, wg + n_wg, ... into bin order (one workgroup).
-// `start` holds every bin's padded start (longest bins first).
+// Scatter of the tiles wg, wg + n_wg, ... into bin order (one workgroup),
+// the next tile's loads in flight while the current one is placed (two
+// buffers used in turn, as in k_bin_count).  `start` holds every bin's
+// padded start (longest bins first).
 __device__ __forceinline__ void bin_scatter(const Batch &bt, const uint32_t *__restrict__ thist,
                                             uint64_t tstride, const uint32_t *start, uint32_t n_id,
                                             unsigned long long *__restrict__ perm,
                                             TxRec *__restrict__ rec, uint32_t *__restrict__ pos_of,
                                             uint64_t wide_min, uint32_t wg, uint32_t n_wg)
 {
-    constexpr int kPer = kTile / kWG;
     __shared__ uint32_t cnt[kBins];
     __shared__ uint32_t base[kBins];
     const Totals T = totals(bt);
-    for (uint64_t tile = wg; tile < T.tiles; tile += n_wg) {
-        const uint32_t b = find_block<0>(bt, T, tile);
-        const DevBlock d = get_block(bt, T, b);
-        const uint64_t i0 = (tile - d.tile0) * kTile;
-        const uint64_t area_end = d.off[d.n];  // end of the block's message area
+    if (wg >= T.tiles) return;  // the whole workgroup
+    // a tile's loads: its transactions, its block, the block's message-area
+    // end, and (lanes below kBins) the tile's transactions of each bin in
+    // earlier tiles
+    struct Tile {
+        TileTx x;
+        DevBlock d;
+        uint32_t b, before;
+        uint64_t t, area_end;
+    };
+    auto load = [&](uint64_t t, Tile &z) {
+        z.t = t;
+        z.b = find_block<0>(bt, T, t);
+        z.d = get_block(bt, T, z.b);
+        load_tile_tx(z.d, (t - z.d.tile0) * kTile, z.x);
+        z.before = ((gptr)thist)[(threadIdx.x < kBins ? threadIdx.x : 0u) * tstride + t];
+        z.area_end = ((gptr64)z.d.off)[z.d.n];
+    };
+    // places tile z while the next one (the last tile: z's again, unused)
+    // loads into y; returns whether there was a next tile
+    auto step = [&](const Tile &z, Tile &y) -> bool {
+        const bool more = z.t + n_wg < T.tiles;  // uniform
+        load(more ? z.t + n_wg : z.t, y);
         if (threadIdx.x < kBins) {
             cnt[threadIdx.x] = 0;
-            // this tile's first position in each bin: the bin's start plus the
-            // transactions of that bin in earlier tiles
-            base[threadIdx.x] = start[threadIdx.x] + thist[threadIdx.x * tstride + tile];
+            base[threadIdx.x] = start[threadIdx.x] + z.before;  // the tile's first position in each bin
         }
         __syncthreads();
+        const uint64_t i0 = (z.t - z.d.tile0) * kTile;
         uint32_t bins[kPer], rank[kPer];
         TxRec r[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
             bins[k] = kBins;
-            if (i < d.n) {
-                const uint64_t a = d.off[i], e = d.off[i + 1];
-                const uint32_t who = d.id[i];
+            if (i < z.d.n) {
+                const uint64_t a = z.x.a[k], e = z.x.e[k];
+                const uint32_t who = z.x.who[k];
                 const bool ok = a <= e && who < n_id;
                 const uint64_t L = ok ? e - a : 0;
-                r[k].addr = reinterpret_cast<uint64_t>(d.msg + a);
+                r[k].addr = reinterpret_cast<uint64_t>(z.d.msg + a);
                 r[k].len = L >= wide_min ? kRecWide
-                                                : (uint32_t)L | (e + kOverread <= area_end ? 0u : kRecNearEnd);
+                                         : (uint32_t)L | (e + kOverread <= z.area_end ? 0u : kRecNearEnd);
                 r[k].id = ok ? who : kRecInvalid;
                 bins[k] = bin_of_length(L);
                 rank[k] = atomicAdd(&cnt[bins[k]], 1u);
@@ -617,12 +680,19 @@ __device__ __forceinline__ void bin_scatter(const Batch &bt, const uint32_t *__r
             if (bins[k] < kBins) {
                 const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
                 const uint32_t pos = base[bins[k]] + rank[k];
-                perm[pos] = ((unsigned long long)b << 40) | i;
+                perm[pos] = ((unsigned long long)z.b << 40) | i;
                 rec[pos] = r[k];
-                pos_of[d.tx0 + i] = pos;
+                pos_of[z.d.tx0 + i] = pos;
             }
         }
         __syncthreads();
+        return more;
+    };
+    Tile za, zb;
+    load(wg, za);
+    for (;;) {
+        if (!step(za, zb)) break;
+        if (!step(zb, za)) break;
     }
 }
 
