@@ -836,24 +836,51 @@ __global__ void __launch_bounds__(kWG) k_finalize(Batch bt, const uint32_t *__re
 {
     const uint32_t lane = lane_id();
     const Totals T = totals(bt);
-    for (uint64_t tile = blockIdx.x; tile < T.tiles; tile += gridDim.x) {
-        const DevBlock d = get_block(bt, T, find_block<0>(bt, T, tile));
-        const uint64_t i0 = (tile - d.tile0) * kTile;
+    if (blockIdx.x >= T.tiles) return;  // the whole workgroup
+    // tiles g, g + G, ...: the next tile's positions load while the current
+    // tile's bits are gathered (two buffers in turn, as in the binning passes;
+    // lanes past a block's end reload its last position and drop the bit)
+    struct Tile {
+        DevBlock d;
+        uint64_t t;
+        uint32_t p[kPer];
+    };
+    auto load = [&](uint64_t t, Tile &z) {
+        z.t = t;
+        z.d = get_block(bt, T, find_block<0>(bt, T, t));
+        const uint64_t i0 = (t - z.d.tile0) * kTile;
+        const gptr src = (gptr)(pos_of + z.d.tx0);
 #pragma unroll
-        for (int it = 0; it < kTile / kWG; ++it) {  // uniform trip count: the ballot sees every lane
-            const uint64_t i = i0 + threadIdx.x + (uint64_t)it * kWG;
-            bool bit = false;
-            if (i < d.n) {
-                const uint32_t p = pos_of[d.tx0 + i];
-                bit = (vperm[p >> 5] >> (p & 31)) & 1u;
-            }
+        for (int k = 0; k < kPer; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+            z.p[k] = src[i < z.d.n ? i : z.d.n - 1];
+        }
+    };
+    auto step = [&](const Tile &z, Tile &y) -> bool {
+        const bool more = z.t + gridDim.x < T.tiles;  // uniform
+        load(more ? z.t + gridDim.x : z.t, y);
+        const uint64_t i0 = (z.t - z.d.tile0) * kTile;
+        uint32_t v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = ((gptr)vperm)[z.p[k] >> 5];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {  // uniform trip count: the ballot sees every lane
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * kWG;
+            const bool bit = i < z.d.n && ((v[k] >> (z.p[k] & 31)) & 1u);
             const unsigned long long m = __ballot(bit);
             const uint64_t base = i - lane;
-            if (lane == 0 && base < d.n) {
-                d.bitmask[base >> 5] = (uint32_t)m;
-                if (base + 32 < d.n) d.bitmask[(base >> 5) + 1] = (uint32_t)(m >> 32);
+            if (lane == 0 && base < z.d.n) {
+                z.d.bitmask[base >> 5] = (uint32_t)m;
+                if (base + 32 < z.d.n) z.d.bitmask[(base >> 5) + 1] = (uint32_t)(m >> 32);
             }
         }
+        return more;
+    };
+    Tile za, zb;
+    load(blockIdx.x, za);
+    for (;;) {
+        if (!step(za, zb)) break;
+        if (!step(zb, za)) break;
     }
 }
 
