@@ -1017,6 +1017,7 @@ def main() -> int:
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),
         "latency_steps": int(len(step_ms)),
+        "latency_ms": [round(float(x), 3) for x in step_ms],
         "ms_per_step_traced": traced_ms,
         # in the binned form with keys derived in the call, the derivation runs
         # on a second stream beside the binning passes: bin_ms covers both and
