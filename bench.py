@@ -900,19 +900,22 @@ def main() -> int:
     torch.cuda.synchronize()
     log("uploaded to %s; workspace %.1f MB" % (dev_name, ws.numel() / 1e6))
 
-    for i in range(max(1, args.warmup)):
+    # warm-up: the first step checked, the others back to back (with the GPU
+    # idle between steps its clock had not settled when the timed run began)
+    ace.verify_batch(ks, [blk], ws, flags)
+    torch.cuda.synchronize()
+    mask, count = blk.result()
+    if count != int(w.truth.sum()) or not np.array_equal(mask, w.truth_bitmask()):
+        log("RESULT MISMATCH: count %d, expected %d" % (count, int(w.truth.sum())))
+        return 1
+    log("warmup step 0 bit-exact with the generator's truth mask (%d valid)" % count)
+    for _ in range(max(1, args.warmup) - 1):
         ace.verify_batch(ks, [blk], ws, flags)
-        torch.cuda.synchronize()
-        if i == 0:
-            mask, count = blk.result()
-            if count != int(w.truth.sum()) or not np.array_equal(mask, w.truth_bitmask()):
-                log("RESULT MISMATCH: count %d, expected %d" % (count, int(w.truth.sum())))
-                return 1
-            log("warmup step 0 bit-exact with the generator's truth mask (%d valid)" % count)
 
     # value: K plain calls back to back between two synchronizations (no stage
-    # events inside the library, no events between the calls); then K more,
-    # each between two stream events, for the step latency percentiles
+    # events inside the library, no events between the calls); then, straight
+    # after, more calls each between two stream events, for the step latency
+    # percentiles (the results are checked after both)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -921,10 +924,6 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    mask, count = blk.result()
-    if count != int(w.truth.sum()) or not np.array_equal(mask, w.truth_bitmask()):
-        log("RESULT MISMATCH after timing")
-        return 1
     n_lat = max(args.steps, 50)   # enough steps for a p99 that is not simply the maximum
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
