@@ -503,11 +503,10 @@ __global__ void __launch_bounds__(kWG) k_zero(Batch bt, Ctrl *ctrl)
 }
 
 // A tile's offsets and identities as the binning passes read them: thread t
-// holds transactions i0 + t + k kWG, k < kPer (those past the block's end
-// are not loaded).  A workgroup loads its next tile into a second TileTx
-// while it bins the current one, so its loads stay in flight across the
-// tile's LDS atomics, barriers and stores (with one tile at a time, a pass
-// over small tiles was bound by how fast workgroups could be started).
+// holds transactions i0 + t + k kWG, k < kPer.  A workgroup loads its next
+// tile into a second TileTx while it bins the current one, so its loads stay
+// in flight across the tile's LDS atomics, barriers and stores (one tile at a
+// time, the passes' waves spent most of their cycles waiting on loads).
 constexpr int kPer = kTile / kWG;
 
 struct TileTx {
