@@ -185,7 +185,7 @@ def openssl_context(w, threads: int, runs: int = 3) -> dict:
         if r == 0:
             ok = np.all(tags == w.tags, axis=1)
             if not np.array_equal(ok, w.truth):
-                raise SystemExit("OpenSSL recomputation disagrees with the generator's truth mask")
+                raise RuntimeError("OpenSSL recomputation disagrees with the generator's truth mask")
         del tags
     one = min(w.n, 200_000)
     single = []
@@ -1035,7 +1035,10 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (about %.0f s)" % args.cpu_seconds)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-        result["cpu_baseline"]["openssl_context"] = openssl_context(w, result["cpu_baseline"]["cores"])
+        try:   # context only: a failure here must not cost the line
+            result["cpu_baseline"]["openssl_context"] = openssl_context(w, result["cpu_baseline"]["cores"])
+        except Exception as e:  # noqa: BLE001
+            result["cpu_baseline"]["openssl_context"] = {"error": str(e)}
     del blk, rev, ks, ws, w
     torch.cuda.empty_cache()
     if not args.no_batching:
