@@ -800,11 +800,17 @@ ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, voi
                            table, n_trees, p.total, nodes);
         if ((rc = launch_status("k_merkle_leaves launch"))) return rc;
     }
-    if (p.levels) {
-        hipLaunchKernelGGL(k_merkle_plan, dim3(p.levels), dim3(kPlanThreads), 0, s, table, n_trees, P);
+    // levels below k0 one launch each over all trees; from k0, where no tree
+    // has more than kTopNodes nodes, one launch for the rest
+    uint32_t k0 = 0;
+    for (uint32_t b = 0; b < n_trees; ++b)
+        while (((trees[b].n_leaves + (1ull << k0) - 1) >> k0) > kTopNodes) ++k0;
+    if (k0 > p.levels) k0 = p.levels;
+    if (k0) {
+        hipLaunchKernelGGL(k_merkle_plan, dim3(k0), dim3(kPlanThreads), 0, s, table, n_trees, P);
         if ((rc = launch_status("k_merkle_plan launch"))) return rc;
     }
-    for (uint32_t k = 0; k < p.levels; ++k) {
+    for (uint32_t k = 0; k < k0; ++k) {
         // this level's pairs over all trees, as the plan kernel counts them
         uint64_t pairs = 0;
         for (uint32_t b = 0; b < n_trees; ++b) {
@@ -815,6 +821,10 @@ ACE_API int ace_merkle_roots(const ace_merkle_tree *trees, uint32_t n_trees, voi
         hipLaunchKernelGGL(k_merkle_level, dim3((unsigned)((pairs + kWG - 1) / kWG)), dim3(kWG), 0, s, table,
                            n_trees, k, P + (uint64_t)k * (n_trees + 1ull), nodes);
         if ((rc = launch_status("k_merkle_level launch"))) return rc;
+    }
+    if (k0 < p.levels) {
+        hipLaunchKernelGGL(k_merkle_top, dim3(n_trees), dim3(kTopWG), 0, s, table, k0, nodes);
+        if ((rc = launch_status("k_merkle_top launch"))) return rc;
     }
     hipLaunchKernelGGL(k_merkle_out, dim3((n_trees + kWG - 1) / kWG), dim3(kWG), 0, s, table, n_trees, nodes);
     return launch_status("k_merkle_out launch");

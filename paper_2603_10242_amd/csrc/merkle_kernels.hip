@@ -17,6 +17,8 @@
 //                    tree's pair count.
 //   k_merkle_level   one parent per lane at level k -> k + 1 (two blocks:
 //                    the 64 child bytes, then the constant padding block).
+//   k_merkle_top     the levels from k0 up, where every tree has at most
+//                    kTopNodes nodes: one workgroup per tree, in LDS.
 //   k_merkle_out     roots to the callers' 32-byte outputs.
 
 namespace ace {
@@ -259,6 +261,61 @@ __global__ void __launch_bounds__(kWG) k_merkle_level(const MerkleDesc *__restri
 #pragma unroll
         for (int j = 0; j < 8; ++j) o[j] = S.h[j];
     }
+}
+
+// The narrow top of every tree in one launch: workgroup b takes tree b from
+// level k0 (at most kTopNodes nodes there) to its root in LDS, one parent per
+// lane and level, and writes the root to the tree's first slot.  One launch
+// per level up there cost more in launches than in hashing.
+constexpr uint32_t kTopWG = 512;
+constexpr uint32_t kTopNodes = 2 * kTopWG;
+__global__ void __launch_bounds__(kTopWG) k_merkle_top(const MerkleDesc *__restrict__ table, uint32_t k0,
+                                                       uint32_t *__restrict__ nodes)
+{
+    __shared__ uint32_t node[kTopNodes][8];
+    const MerkleDesc d = table[blockIdx.x];
+    const uint32_t t = threadIdx.x;
+    // nodes of the tree at level k0 (the host picks k0 so that m <= kTopNodes)
+    uint32_t m = d.n ? (uint32_t)((d.n + (1ull << k0) - 1) >> k0) : 0u;
+    if (m <= 1) return;  // the whole workgroup: the root is already in place
+    for (uint32_t j = t; j < m; j += kTopWG) {
+        const uint32_t *q = nodes + 8ull * (d.leaf0 + ((uint64_t)j << k0));
+        const U4 a = load16(q), b = load16(q + 4);
+        node[j][0] = a.x; node[j][1] = a.y; node[j][2] = a.z; node[j][3] = a.w;
+        node[j][4] = b.x; node[j][5] = b.y; node[j][6] = b.z; node[j][7] = b.w;
+    }
+    __syncthreads();
+    while (m > 1) {  // uniform
+        const uint32_t pairs = m >> 1;
+        const bool act = t < pairs;
+        State S = initial_state();
+        if (act) {
+            uint32_t W[16];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                W[j] = node[2 * t][j];
+                W[8 + j] = node[2 * t + 1][j];
+            }
+            compress_block(S, W);
+            compress_pad64(S);  // the 64-byte message's padding block
+        }
+        // an unpaired last node moves up unchanged, to index `pairs`
+        uint32_t carry[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) carry[j] = node[m - 1][j];
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) node[t][j] = S.h[j];
+        }
+        if ((m & 1) && t == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) node[pairs][j] = carry[j];
+        }
+        __syncthreads();
+        m = pairs + (m & 1);
+    }
+    if (t < 8) nodes[8ull * d.leaf0 + t] = node[0][t];
 }
 
 __global__ void __launch_bounds__(kWG) k_merkle_out(const MerkleDesc *__restrict__ table,

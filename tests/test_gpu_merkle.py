@@ -89,6 +89,16 @@ def test_large_trees_and_empty_trees(ace):
     assert np.array_equal(gpu_roots(ace, data, off, sizes), oracle.merkle_roots(data, off, sizes))
 
 
+@pytest.mark.parametrize("sizes", [[1024], [1025], [2048], [2049], [1023, 1024, 1025, 2047, 2048, 2049, 3]])
+def test_sizes_around_the_top_levels(ace, sizes):
+    """Trees around the width at which the levels move into one launch (a
+    workgroup per tree holding at most 1,024 nodes in LDS): exactly 1,024
+    nodes at the first of those levels, one more, and mixes of both."""
+    note("merkle top-level boundaries %s" % sizes)
+    data, off = forest(64, sizes, lo=0, hi=90)
+    assert np.array_equal(gpu_roots(ace, data, off, sizes), oracle.merkle_roots(data, off, sizes))
+
+
 def test_decreasing_offsets_hash_as_empty(ace):
     note("merkle decreasing offsets")
     data = np.arange(40, dtype=np.uint8)
