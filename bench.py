@@ -662,7 +662,7 @@ def bench_merkle(args) -> dict:
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "Merkle roots of 256 blocks (%d attestation records of 72 B)" % n,
                    "blocks": int(sizes.size), "leaves": n},
-        "roofline": {"kernel": "k_merkle_leaves + k_merkle_level", "bound": "alu",
+        "roofline": {"kernel": "k_merkle_leaves + k_merkle_level + k_merkle_top", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_INT32_TOPS,
                      "unit": "T int32 lane-instr/s", "frac": achieved / PEAK_INT32_TOPS,
                      "traffic": None,
