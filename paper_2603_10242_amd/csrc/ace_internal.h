@@ -96,10 +96,13 @@ struct MultiHkdf {
 };
 
 // Derived per-workgroup constants of an HKDF parameter set (built in LDS).
+// The expand blocks (info || 0x01 and its padding) are the same for every
+// identity, so they are held as their whole schedules with the round
+// constants added: info_kw[q][t] = K[t] + W_q[t].
 struct HkdfPrep {
     uint32_t salt_ipad[8];
     uint32_t salt_opad[8];
-    uint32_t info_words[kMaxInfoBlocks][16];
+    alignas(16) uint32_t info_kw[kMaxInfoBlocks][64];
     uint32_t info_blocks;
 };
 

@@ -80,15 +80,44 @@ __device__ void hkdf_prepare(const Params &hp, HkdfPrep &out)
     }
     // Expand input T(1) = HMAC(PRK, info || 0x01): after the 64-byte key
     // block the hashed stream is info || 0x01, bit length (64 + len + 1) * 8.
+    // Each of its blocks is stored as K[t] + W[t] for all 64 rounds (FIPS
+    // 180-4 sec. 6.2.2 steps 1 and 3 with the message-dependent part done once).
     const uint32_t il = hp.info_len;
     const uint32_t nq = (il + 1 + 9 + 63) / 64;
     if (lane_id() == 0) {
-        for (uint32_t q = 0; q < nq; ++q)
-            for (uint32_t j = 0; j < 16; ++j)
-                out.info_words[q][j] =
-                    padded_word(hp.info, il, 0x01u, 1, 16 * q + j, nq, 8ull * (64 + il + 1));
+        for (uint32_t q = 0; q < nq; ++q) {
+            uint32_t W[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                W[j] = padded_word(hp.info, il, 0x01u, 1, 16 * q + j, nq, 8ull * (64 + il + 1));
+#pragma unroll
+            for (int t = 0; t < 64; ++t) {
+                if (t >= 16)
+                    W[t & 15] = small_sigma1(W[(t - 2) & 15]) + W[(t - 7) & 15] +
+                                small_sigma0(W[(t - 15) & 15]) + W[t & 15];
+                out.info_kw[q][t] = W[t & 15] + kRound[t];
+            }
+        }
         out.info_blocks = nq;
     }
+}
+
+// F(s, B) for a block B whose schedule is the same on every lane, given as
+// kw[t] = K[t] + W[t]: only the 64 rounds run per lane (about 900 instead of
+// 1,384 VALU instructions).  kw lives in LDS; sixteen words are read per
+// iteration of the round loop.
+__device__ __forceinline__ void compress_kw(State &s, const uint32_t *kw)
+{
+    uint32_t a = s.h[0], b = s.h[1], c = s.h[2], d = s.h[3];
+    uint32_t e = s.h[4], f = s.h[5], g = s.h[6], h = s.h[7];
+#pragma nounroll
+    for (int q = 0; q < 4; ++q) {
+        const RoundConsts16 kq = *reinterpret_cast<const RoundConsts16 *>(kw + 16 * q);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) round_step(a, b, c, d, e, f, g, h, 0u, kq.k[j]);
+    }
+    s.h[0] += a; s.h[1] += b; s.h[2] += c; s.h[3] += d;
+    s.h[4] += e; s.h[5] += f; s.h[6] += g; s.h[7] += h;
 }
 
 // HMAC midstate F(IV, K0 ^ pad) of a 32-byte key held as state words
@@ -145,12 +174,7 @@ __device__ __forceinline__ void derive_lane(bool live, const uint32_t (&rv)[8], 
     State pi, po;
     hmac_midstates(prk, pi, po);
     const uint32_t nq = P.info_blocks;
-    for (uint32_t q = 0; q < nq; ++q) {
-        uint32_t W[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) W[j] = P.info_words[q][j];
-        compress_block(pi, W);
-    }
+    for (uint32_t q = 0; q < nq; ++q) compress_kw(pi, P.info_kw[q]);
     compress_tail32(po, pi);  // po = k
 #pragma unroll
     for (int i = 0; i < 8; ++i) key[i] = po.h[i];
