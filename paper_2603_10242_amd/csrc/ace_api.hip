@@ -48,6 +48,12 @@ int launch_status(const char *what) { return check_hip(hipGetLastError(), what);
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Workgroups per CU of a key derivation that has the GPU to itself: four
+// waves per SIMD, the kernel's lanes striding over the identities, so that
+// every wave derives the same number of keys (a million identities in waves of
+// one each are 3.2 rounds of the five-wave slots, the last one a fifth full).
+constexpr unsigned kDeriveWgsPerCu = 4;
+
 // Compute units of the current device (cached per device).
 int cu_count()
 {
@@ -431,7 +437,8 @@ int enqueue_stages(const Plan &p, const Batch &bt, const ace_keyset *keys, const
     } else {
         uint32_t *mid = reinterpret_cast<uint32_t *>(ws + p.off_mid);
         if (keys->n_id) {
-            unsigned g = (unsigned)((keys->n_id + kWG - 1) / kWG);
+            unsigned g = std::min<unsigned>((unsigned)((keys->n_id + kWG - 1) / kWG),
+                                            kDeriveWgsPerCu * cus);
             hipStream_t ds = s;
             if (fork && binned && (graph || p.total_tx) && (fk = fork_ctx())) {
                 if ((rc = check_hip(hipEventRecord(fk->fork, s), "hipEventRecord"))) return rc;
@@ -638,7 +645,8 @@ ACE_API int ace_derive_keys(const uint8_t *d_rev, uint32_t n_id, const uint8_t *
     if (!aligned(d_rev, 4) || (d_key_out && !aligned(d_key_out, 4)) || (d_mid_out && !aligned(d_mid_out, 4)))
         return fail(ACE_ERR_INVALID_ARG, "misaligned device array");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const unsigned grid = (unsigned)((n_id + kWG - 1) / kWG);
+    const unsigned grid = std::min<unsigned>((unsigned)((n_id + kWG - 1) / kWG),
+                                             kDeriveWgsPerCu * (unsigned)cu_count());
     hipLaunchKernelGGL(k_derive, dim3(grid), dim3(kWG), 0, s, d_rev, n_id, d_key_out, d_mid_out, hp);
     return launch_status("k_derive launch");
 }

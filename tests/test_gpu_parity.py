@@ -103,6 +103,26 @@ def test_derive_keys_infos(ace, info):
     assert np.array_equal(key.cpu().numpy(), oracle.derive_keys(rev, salt, info, 8))
 
 
+@pytest.mark.parametrize("n_id", [262143, 262145, 600001])
+def test_derive_keys_strided_passes(ace, n_id):
+    """More identities than the derivation's capped grid has lanes (four
+    256-lane workgroups per CU, 262,144 lanes on 256 CUs): lanes take one,
+    two or three identities, the last pass ragged.  Every key and midstate
+    against the oracle."""
+    import torch
+    note("derive_keys strided n_id=%d" % n_id)
+    r = np.random.Generator(np.random.PCG64(n_id))
+    rev = r.integers(0, 256, size=(n_id, 32), dtype=np.uint8)
+    salt = r.integers(0, 256, size=32, dtype=np.uint8).tobytes()
+    key = torch.zeros((n_id, 32), dtype=torch.uint8, device="cuda")
+    mid = torch.zeros((n_id, 16), dtype=torch.int32, device="cuda")
+    ace.derive_keys(ace.to_device(rev), salt, W.INFO_ATTEST, key_out=key, mid_out=mid)
+    torch.cuda.synchronize()
+    okeys = oracle.derive_keys(rev, salt, W.INFO_ATTEST, 8)
+    assert np.array_equal(key.cpu().numpy(), okeys)
+    assert np.array_equal(mid.cpu().numpy().view(np.uint32), oracle.hmac_midstates(okeys))
+
+
 def test_derive_keys_match_openssl_client_keys(ace):
     import torch
     w = W.config1()
