@@ -285,20 +285,31 @@ __device__ __forceinline__ void message_blocks(State &S, bool live, bool overrea
             --avail;
             if (rb < 64) {
                 // padding: word jf holds byte rb (the 0x80 marker) after its c
-                // message bytes; earlier words are message, later ones zero
+                // message bytes; earlier words are message, later ones zero.
+                // In the last block the marker is in words 0..13 (or was in the
+                // block before: jf < 0) and words 14..15 hold the bit length;
+                // in a block before it, the message fills 56..63 bytes, so only
+                // words 14..15 change.  (Lanes of a binned wave share their
+                // block count, so one of the two branches runs per block.)
                 const int32_t r0 = (int32_t)rb;
                 const int32_t jf = r0 >> 2;   // negative: the marker was in the previous block
                 const uint32_t c8 = ((uint32_t)r0 & 3u) << 3;
                 const uint32_t keep = ~(0xFFFFFFFFu >> c8);
                 const uint32_t pad = 0x80000000u >> c8;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const uint32_t part = (W[j] & keep) | pad;
-                    W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
-                }
                 if (b + 1 == g.nb) {
+#pragma unroll
+                    for (int j = 0; j < 14; ++j) {
+                        const uint32_t part = (W[j] & keep) | pad;
+                        W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
+                    }
                     W[14] = g.len_hi;
                     W[15] = g.len_lo;
+                } else {
+#pragma unroll
+                    for (int j = 14; j < 16; ++j) {
+                        const uint32_t part = (W[j] & keep) | pad;
+                        W[j] = j < jf ? W[j] : (j == jf ? part : 0u);
+                    }
                 }
             }
             compress_block(S, W);
