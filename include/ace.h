@@ -235,7 +235,8 @@ ACE_API int ace_verify_batch_noalloc(const ace_keyset *keys, const ace_block *bl
  *                      verify kernel
  *   derive_wgs_per_cu  workgroups per CU of the key derivation while it runs
  *                      beside the binning passes (keys derived in a binned
- *                      call); 0: one workgroup per 256 identities
+ *                      call); 0: as with the GPU to itself (at most four
+ *                      per CU, each lane striding over the identities)
  *   wide_min_len       binned calls: messages of at least this many bytes are
  *                      verified from their block's offsets instead of the
  *                      32-bit length of the bin-order record.  Default and

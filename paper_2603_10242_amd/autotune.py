@@ -191,7 +191,8 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
             best_aux = (t, apc)
 
     # 4. key derivation beside the binning passes (keys derived in the call):
-    # workgroups per CU, 0 = one workgroup per 256 identities.  Measured on the
+    # workgroups per CU, 0 = as with the GPU to itself (at most four per CU,
+    # lanes striding over the identities).  Measured on the
     # throughput sweep's batch (16M transactions, 1M identities): the best
     # share depends on how long the binning passes run beside the derivation,
     # and at 4M transactions they end well before it.

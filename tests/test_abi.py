@@ -263,7 +263,7 @@ def test_tuning_roundtrip_and_limits(lib):
             ace.set_tuning(verify_wgs_per_cu=0)
         with pytest.raises(ace.AceError):
             ace.set_tuning(aux_wgs_per_cu=65)
-        ace.set_tuning(derive_wgs_per_cu=0)          # 0: one workgroup per 256 identities
+        ace.set_tuning(derive_wgs_per_cu=0)          # 0: the library's own grid
         assert ace.get_tuning()["derive_wgs_per_cu"] == 0
         with pytest.raises(ace.AceError):
             ace.set_tuning(derive_wgs_per_cu=65)
