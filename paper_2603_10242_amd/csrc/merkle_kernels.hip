@@ -82,18 +82,39 @@ __global__ void k_merkle_put(MerkleDesc *table, MerkleChunk c)
     if (t < c.count) table[c.first + t] = c.d[t];
 }
 
-// Last tree whose first leaf is <= g (trees with no leaves are skipped by
-// taking the last of equal starts).
-__device__ __forceinline__ uint32_t merkle_tree_of(const MerkleDesc *table, uint32_t n_trees,
-                                                   uint64_t g)
+// Last i < n with key(i) <= x, for keys that do not decrease (equal keys:
+// the last of them).  The lanes of a wave hold consecutive x, so the first
+// active lane's x is searched once for the wave (a uniform loop on scalar
+// loads); only lanes at or past the next key (a wave across two trees)
+// search again, each on its own.
+template <class Key>
+__device__ __forceinline__ uint32_t last_at_or_below(uint32_t n, uint64_t x, Key key)
 {
-    uint32_t lo = 0, hi = n_trees;  // answer in [lo, hi)
+    const uint64_t x0 = uniform64(x);
+    uint32_t lo = 0, hi = n;  // answer in [lo, hi)
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (table[mid].leaf0 <= g) lo = mid;
+        if (key(mid) <= x0) lo = mid;
         else hi = mid;
     }
+    if (lo + 1 < n && key(lo + 1) <= x) {
+        uint32_t l = lo + 1, h = n;
+        while (h - l > 1) {
+            const uint32_t mid = (l + h) >> 1;
+            if (key(mid) <= x) l = mid;
+            else h = mid;
+        }
+        return l;
+    }
     return lo;
+}
+
+// Tree of leaf g: the last tree whose first leaf is <= g (trees with no
+// leaves are skipped by taking the last of equal starts).
+__device__ __forceinline__ uint32_t merkle_tree_of(const MerkleDesc *__restrict__ table,
+                                                   uint32_t n_trees, uint64_t g)
+{
+    return last_at_or_below(n_trees, g, [&](uint32_t i) { return table[i].leaf0; });
 }
 
 // SHA-256 of L bytes at p into S (from the initial value).  With
@@ -232,12 +253,7 @@ __global__ void __launch_bounds__(kWG) k_merkle_level(const MerkleDesc *__restri
     uint64_t left = 0;
     if (live) {
         // last tree whose prefix is <= q
-        uint32_t lo = 0, hi = n_trees;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (Pk[mid] <= q) lo = mid;
-            else hi = mid;
-        }
+        const uint32_t lo = last_at_or_below(n_trees, q, [&](uint32_t i) { return Pk[i]; });
         const uint64_t p = q - Pk[lo];
         left = table[lo].leaf0 + ((2 * p) << k);
         const uint64_t right = left + (1ull << k);
