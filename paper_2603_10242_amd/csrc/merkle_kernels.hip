@@ -178,6 +178,43 @@ __device__ __forceinline__ void sha256_bytes(bool live, const uint8_t *p, uint64
     }
 }
 
+// SHA-256 of a 72-byte leaf at p (4-byte alignment not required): the
+// paper form's check record, obj_hash (32) || domain (8) || credential (32),
+// the leaf of an attestation root.  Its second block holds 8 record bytes,
+// then the 0x80 marker, zeros and the bit length 576: words 2..15 are
+// constants there and fold into that block's schedule.  The 19 dwords from
+// the aligned start hold the record at any alignment; the last one is read
+// only when it holds record bytes.
+constexpr uint64_t kRecordLeaf = 72;
+__device__ __forceinline__ void sha256_record72(const uint8_t *p, State &S)
+{
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+    const uint32_t sh = (uint32_t)addr & 3u;
+    const uint32_t sel = 0x00010203u + sh * 0x01010101u;
+    const uint32_t *A0 = reinterpret_cast<const uint32_t *>(addr - sh);
+    uint32_t D[19];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const U4 v = load16(A0 + 4 * c);
+        D[4 * c] = v.x; D[4 * c + 1] = v.y; D[4 * c + 2] = v.z; D[4 * c + 3] = v.w;
+    }
+    D[16] = load32(A0 + 16);
+    D[17] = load32(A0 + 17);
+    D[18] = load32(A0 + (sh ? 18 : 17));
+    uint32_t W[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) W[j] = __builtin_amdgcn_perm(D[j + 1], D[j], sel);
+    S = initial_state();
+    compress_block(S, W);
+    W[0] = __builtin_amdgcn_perm(D[17], D[16], sel);
+    W[1] = __builtin_amdgcn_perm(D[18], D[17], sel);
+    W[2] = 0x80000000u;
+#pragma unroll
+    for (int j = 3; j < 15; ++j) W[j] = 0u;
+    W[15] = (uint32_t)(kRecordLeaf * 8);
+    compress_fold(S, W);
+}
+
 __global__ void __launch_bounds__(kWG) k_merkle_leaves(const MerkleDesc *__restrict__ table,
                                                        uint32_t n_trees, uint64_t n_leaves,
                                                        uint32_t *__restrict__ nodes)
@@ -198,7 +235,12 @@ __global__ void __launch_bounds__(kWG) k_merkle_leaves(const MerkleDesc *__restr
         overread_ok = e >= a && a + L + 80 <= d.off[d.n];
     }
     State S;
-    sha256_bytes(live, p, L, S, overread_ok);
+    if (__ballot(live && L != kRecordLeaf) == 0) {
+        // every live leaf of the wave is a 72-byte record
+        if (live) sha256_record72(p, S);
+    } else {
+        sha256_bytes(live, p, L, S, overread_ok);
+    }
     if (live) {
         uint32_t *q = nodes + 8ull * g;
 #pragma unroll

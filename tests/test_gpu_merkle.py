@@ -68,6 +68,27 @@ def test_every_tree_size_0_to_300(ace, separate):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("lead", [0, 1, 2, 3])
+def test_record_leaves_every_alignment(ace, lead):
+    """72-byte leaves (the check records of the paper form) starting at each
+    byte alignment, in waves of 72-byte leaves only and in waves where a few
+    leaves have other lengths (65, 71, 73, 119, 0), so that both leaf paths
+    run; the last record ends the data (no bytes past it)."""
+    note("merkle record leaves lead=%d" % lead)
+    r = np.random.Generator(np.random.PCG64(720 + lead))
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 700, 1000]
+    lens = np.full(int(np.sum(sizes)), 72, np.int64)
+    odd = r.choice(lens.size, size=40, replace=False)
+    lens[odd[odd > 1300]] = r.choice([65, 71, 73, 119, 0], size=int(np.sum(odd > 1300)))
+    off = np.zeros(lens.size + 1, np.uint64)
+    np.cumsum(lens, out=off[1:])
+    off += lead
+    data = r.integers(0, 256, size=int(off[-1]), dtype=np.uint8)
+    for separate in (False, True):
+        got = gpu_roots(ace, data, off, sizes, separate)
+        assert np.array_equal(got, oracle.merkle_roots(data, off, sizes))
+
+
 def test_leaf_lengths_0_to_300_misaligned(ace):
     """Leaves of every length 0..300 (each padding case) at every alignment."""
     note("merkle leaf lengths")
