@@ -201,7 +201,7 @@ def run(sizes=(4096, 16384, 65536, 262144, 1 << 20, 4 << 20), big: int = 4 << 20
     dblk = ace.upload_block(wd.msg, wd.off, wd.ids, wd.tags)
     rks = ace.rev_keyset(ace.to_device(wd.rev), wd.salt, wd.info)
     best_der = (float("inf"), default.get("derive_wgs_per_cu", 1))
-    for dpc in (0, 1, 2, 4):
+    for dpc in (0, 1, 2, 3, 4):
         ace.set_tuning(derive_wgs_per_cu=dpc)
         t = _time(lambda: ace.verify_batch(rks, [dblk], flags=ace.ACE_BUCKETED))
         meas.append({"n": derive_n, "n_id": int(wd.n_id), "derive_wgs_per_cu": dpc, "ms": t})

@@ -556,6 +556,11 @@ __global__ void __launch_bounds__(kWG) k_bin_count(Batch bt, uint32_t *__restric
                                                    uint64_t tstride, uint32_t n_id)
 {
     __shared__ uint32_t h[kBins];
+    // The binning passes run beside the key derivation (the caller's
+    // stream and the second one): their waves, mostly waiting on memory,
+    // issue first whenever they are ready, and the derivation's waves take
+    // the remaining issue slots.
+    __builtin_amdgcn_s_setprio(3);
     const Totals T = totals(bt);
     if (blockIdx.x >= T.tiles) return;  // the whole workgroup
     // Two buffers used in turn (the loop body twice, no copies between them):
@@ -597,6 +602,7 @@ __global__ void __launch_bounds__(kScanWG) k_bin_scan(Batch bt, Ctrl *ctrl,
                                                       uint32_t *__restrict__ thist, uint64_t tstride)
 {
     __shared__ uint32_t part[kScanWG];
+    __builtin_amdgcn_s_setprio(3);  // as in k_bin_count
     const uint32_t bin = blockIdx.x;
     const uint32_t t = threadIdx.x;
     const Totals T = totals(bt);
@@ -713,6 +719,7 @@ __global__ void __launch_bounds__(kWG) k_bin_scatter(Batch bt, Ctrl *ctrl,
                                                      TxRec *__restrict__ rec,
                                                      uint32_t *__restrict__ pos_of, uint64_t wide_min)
 {
+    __builtin_amdgcn_s_setprio(3);  // as in k_bin_count
     // bin layout from the totals: order o = 63 - bin, longest first, each bin
     // padded to a multiple of 64; workgroup 0 publishes it for the verify pass
     __shared__ uint32_t pad[kBins];
