@@ -81,7 +81,7 @@ ace_tuning g_tune = {
     /* verify_wgs_per_cu */ 8,
     /* aux_wgs_per_cu    */ 8,
     /* auto_persistent   */ 0,
-    /* derive_wgs_per_cu */ 1,
+    /* derive_wgs_per_cu */ 4,
     /* wide_min_len      */ kRecMaxLen,
     /* grab_cap          */ {0},
 };
